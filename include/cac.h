@@ -1,0 +1,177 @@
+/*
+ * cac.h -- C ABI of libcac, the MI355X (gfx950) implementation of one coupled
+ * time step of the conservative Allen-Cahn lattice Boltzmann method with
+ * geometric ghost-node wetting and global phase-field volume correction
+ * (Bello, Mander, Lauricella, Guglielmo, La Rocca, Montessori, "Accurate
+ * wetting dynamics via a conservative Allen-Cahn based lattice Boltzmann
+ * approach for multiphase flows", Sec. II).
+ *
+ * Problem statement the calls follow (Sec. II B, II C): a voxel mask splits
+ * the lattice into fluid nodes and solid nodes; every solid node with a fluid
+ * neighbour (a "wall node") carries a prescribed contact angle theta; the
+ * conserved observable is the phase-field volume M = sum over fluid nodes of
+ * phi (Eq. (48)).
+ *
+ * Conventions
+ *  - Lattice nx * ny * nz, node index n = x + nx * (y + ny * z), periodic
+ *    index wrap in x, y and z (walls are solid voxels in the mask).
+ *  - Vector and population fields are structure of arrays: u[d * N + n],
+ *    f[i * N + n] with the D3Q27 velocities in the order
+ *      0 (0,0,0); 1,2 (+-1,0,0); 3,4 (0,+-1,0); 5,6 (0,0,+-1);
+ *      7,8 +-(1,1,0); 9,10 +-(1,-1,0); 11,12 +-(1,0,1); 13,14 +-(1,0,-1);
+ *      15,16 +-(0,1,1); 17,18 +-(0,1,-1); 19,20 +-(1,1,1); 21,22 +-(1,1,-1);
+ *      23,24 +-(1,-1,1); 25,26 +-(-1,1,1).
+ *  - Pointers named d_* are device pointers (HIP global memory on the device
+ *    the handle was created on); all others are host pointers.
+ *  - Calls on a handle are stream-ordered on the stream given to cac_init and
+ *    asynchronous unless stated; a handle is used by one host thread at a time.
+ *  - The library never frees caller buffers.  Device memory of the handle is
+ *    obtained through the allocation callback (or hipMalloc when it is NULL)
+ *    and released by cac_destroy (callback memory: the caller's to release).
+ *  - Every call returns a cac_status; on failure a message is kept for
+ *    cac_last_error.  Device-side non-finite detection is reported by the next
+ *    synchronising call (cac_volume, cac_sync).
+ */
+#ifndef CAC_H
+#define CAC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CAC_OK = 0,
+    CAC_ERR_ARG = 1,       /* invalid argument (null pointer, size, range) */
+    CAC_ERR_GEOMETRY = 2,  /* unusable mask (no fluid node, wrong size) */
+    CAC_ERR_HIP = 3,       /* a HIP runtime call failed */
+    CAC_ERR_NONFINITE = 4, /* a NaN/Inf appeared in phi or u (watchdog flag) */
+    CAC_ERR_STATE = 5,     /* call out of order (e.g. step before set_state) */
+    CAC_ERR_ALLOC = 6      /* the allocation callback or hipMalloc failed */
+} cac_status;
+
+typedef struct cac_handle cac_handle;
+
+/* Allocation callback: returns `bytes` of device memory (256-byte aligned) that
+ * stays valid until cac_destroy, or NULL on failure. */
+typedef void *(*cac_alloc_fn)(size_t bytes, void *user);
+
+/* Physical and numerical parameters, lattice units (dx = dt = 1). */
+typedef struct {
+    double rho_l, rho_g;     /* liquid (phi = 1) and gas (phi = 0) densities, Eq. (8) */
+    double nu_l, nu_g;       /* kinematic viscosities; mu = rho nu interpolated linearly, Eqs. (9)-(10) */
+    double sigma, delta;     /* surface tension and interface width: beta = 12 sigma/delta,
+                                kappa_phi = 3 sigma delta / 2 (definitions after Eq. (19)) */
+    double D;                /* CAC interface diffusivity, Eq. (24); kappa = 4 D / delta, Eq. (26) */
+    double g[3];             /* body acceleration; F_ext = (rho(phi) - rho_g) g */
+    double eps_phi;          /* interface band of the volume correction, Eq. (51) (default 1e-3) */
+    double eps_n;            /* interface normal is zero where |grad phi| <= eps_n (default 1e-12) */
+    double sin_tol, cot_max; /* cot(theta_c) -> sign(cos) cot_max where |sin| < sin_tol (text after Eq. (45)) */
+    int volume_correction;   /* 1: apply the correction of Eq. (53) every step */
+    int wall_compression;    /* compressive flux phi(1-phi)n on wall nodes: 0 -> zero,
+                                1 -> g (1 - g) times the unit corrected gradient of Eq. (45) */
+} cac_params;
+
+/* Fill p with the defaults (rho = 1, nu = 0.04, sigma = 0.02, delta = 4,
+ * D = 0.1, g = 0, eps_phi = 1e-3, eps_n = 1e-12, sin_tol = 1e-6,
+ * cot_max = 1e6, volume_correction = 1, wall_compression = 1). */
+cac_status cac_default_params(cac_params *p);
+
+/* Create a handle for an nx * ny * nz lattice on the current HIP device.
+ * hip_stream: hipStream_t to order all work on (NULL: the null stream).
+ * alloc/alloc_user: allocation callback (NULL: hipMalloc, freed by cac_destroy).
+ * Errors: CAC_ERR_ARG if a size is < 2 or 27 * N does not fit in 31 bits, or
+ * a parameter is out of range (densities or viscosities <= 0, delta <= 0, D < 0). */
+cac_status cac_init(cac_handle **h, int nx, int ny, int nz, const cac_params *p, cac_alloc_fn alloc,
+                    void *alloc_user, void *hip_stream);
+
+/* Set the geometry.  solid: host, N bytes, 1 = solid, 0 = fluid.
+ * theta_rad: host, N floats, prescribed contact angle in radians measured
+ * through the liquid (phi = 1), read only at wall nodes; NULL = pi/2.
+ * Builds, on the host, the wall-node list in ascending node index: the
+ * unnormalised wall normal of Eq. (36) (weights of Eq. (37)), its unit vector
+ * (Eq. (38)) and the donor link of Eqs. (39)-(41), chosen among all fluid links
+ * by exact integer comparison of the alignment scores, ties to the lowest link
+ * index.  Wall nodes whose normal sums to zero are kept in the list but skipped
+ * by the update (their ghost stays at its initial value); their count is in the
+ * cac_last_error text.  Invalidates the state (call cac_set_state next).
+ * Errors: CAC_ERR_ARG (null solid), CAC_ERR_GEOMETRY (no fluid node). */
+cac_status cac_set_geometry(cac_handle *h, const uint8_t *solid, const float *theta_rad);
+
+/* Number of wall nodes n_b (skipped ones included). */
+cac_status cac_num_wall_nodes(cac_handle *h, int *n_b);
+
+/* Wall-node tables (host outputs, any may be NULL): linear_index[n_b],
+ * normal6[3 n_b] (six times the unnormalised wall normal, exact integers),
+ * donor[n_b] (donor link index 1..26, or -1 when skipped). */
+cac_status cac_wall_nodes(cac_handle *h, int32_t *linear_index, int32_t *normal6, int32_t *donor);
+
+/* Handle-free host version of the wall-node tables (no GPU use): for the
+ * mask solid (host, N bytes) writes n_b and, when cap >= n_b, the tables of
+ * cac_wall_nodes.  Errors: CAC_ERR_ARG (bad size or null pointer). */
+cac_status cac_wall_tables(int nx, int ny, int nz, const uint8_t *solid, int *n_b, int32_t *linear_index,
+                           int32_t *normal6, int32_t *donor, int cap);
+
+/* Replace the contact angles: d_theta_compact, device, n_b floats (radians),
+ * in wall-node order.  Takes effect at the next step. */
+cac_status cac_set_contact_angles(cac_handle *h, const float *d_theta_compact);
+
+/* Initial state.  d_phi: device, N floats, phi on all nodes (the values on
+ * wall nodes are the initial ghosts).  d_u (3N) and d_pstar (N): initial
+ * velocity and reduced pressure p* (Eq. (5)), or NULL for zero.  Populations
+ * start at the equilibrium of Eq. (11); the target volume M_target is the sum
+ * of d_phi over fluid nodes (FP64).  Errors: CAC_ERR_STATE before
+ * cac_set_geometry, CAC_ERR_ARG for a null d_phi. */
+cac_status cac_set_state(cac_handle *h, const float *d_phi, const float *d_u, const float *d_pstar);
+
+/* Advance nsteps coupled steps (ghost update W, hydrodynamic collide-stream H,
+ * CAC update P, volume correction V; Sec. II).  Asynchronous.
+ * Errors: CAC_ERR_STATE without a state, CAC_ERR_ARG for nsteps < 0,
+ * CAC_ERR_HIP on a launch failure. */
+cac_status cac_step(cac_handle *h, int nsteps);
+
+/* Phase-field volume M = sum over fluid nodes of phi (Eq. (48)), accumulated
+ * in FP64 in a fixed order.  Synchronises the stream; returns
+ * CAC_ERR_NONFINITE if the watchdog flag is set. */
+cac_status cac_volume(cac_handle *h, double *out_host);
+
+/* Copy out the current fields (device outputs, any may be NULL): d_phi (N) =
+ * phi on fluid nodes and the latest ghosts on wall nodes; d_u (3N) and
+ * d_pstar (N) = velocity (Eq. (7)) and p* (Eq. (6)) of the last step (the
+ * initial ones before any step).  Asynchronous. */
+cac_status cac_get_fields(cac_handle *h, float *d_phi, float *d_u, float *d_pstar);
+
+/* Copy out the post-collision populations of the last step (device, 27 N),
+ * defined on fluid nodes. */
+cac_status cac_get_populations(cac_handle *h, float *d_f);
+
+/* Wait for the handle's stream and report the watchdog flag
+ * (CAC_ERR_NONFINITE) and any deferred HIP error. */
+cac_status cac_sync(cac_handle *h);
+
+/* Launch shape of the bulk kernels: tile bx * by * bz nodes per workgroup
+ * (product 64..1024, bx a multiple of 16).  use_graph: 1 = replay steps from a
+ * captured HIP graph.  Errors: CAC_ERR_ARG for an unsupported shape. */
+cac_status cac_set_launch(cac_handle *h, int bx, int by, int bz, int use_graph);
+
+/* Advance nsteps steps like cac_step, with HIP events recorded on the
+ * handle's stream around every kernel; adds the elapsed milliseconds of each
+ * substep kernel to ms[0..3] (W ghosts, H hydrodynamics, P phase field,
+ * V volume correction).  Synchronises.  For measurement only. */
+cac_status cac_profile_step(cac_handle *h, int nsteps, double *ms);
+
+/* Release the handle and the device memory it allocated itself. */
+cac_status cac_destroy(cac_handle *h);
+
+const char *cac_status_string(cac_status s);
+
+/* Copy the message of the last failed call on h into buf (n bytes). */
+cac_status cac_last_error(cac_handle *h, char *buf, size_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CAC_H */

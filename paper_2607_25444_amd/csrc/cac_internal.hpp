@@ -1,0 +1,110 @@
+// cac_internal.hpp -- declarations shared by the HIP kernels and the host
+// runtime of libcac (gfx950).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <utility>
+
+namespace cac {
+
+// ---------------------------------------------------------------- D3Q27 set
+// Canonical order: 0 rest; 1..6 axis pairs; 7..18 face-diagonal pairs;
+// 19..26 body-diagonal pairs; the opposite of odd i is i + 1.
+struct Lat {
+    static constexpr int Q = 27;
+    static constexpr int cx[27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, -1, 1};
+    static constexpr int cy[27] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, -1, 1, 1, -1};
+    static constexpr int cz[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1, 1, -1, -1, 1, 1, -1, 1, -1};
+    __host__ __device__ static constexpr int norm2(int i) { return cx[i] * cx[i] + cy[i] * cy[i] + cz[i] * cz[i]; }
+    __host__ __device__ static constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+    // lattice weight as a rational: w = 8/27, 2/27, 1/54, 1/216 by |c|^2
+    __host__ __device__ static constexpr float w(int i)
+    {
+        return norm2(i) == 0 ? 8.0f / 27.0f : norm2(i) == 1 ? 2.0f / 27.0f : norm2(i) == 2 ? 1.0f / 54.0f : 1.0f / 216.0f;
+    }
+    // link index of the offset (dx, dy, dz) in {-1,0,1}^3
+    __host__ __device__ static constexpr int idx(int dx, int dy, int dz)
+    {
+        for (int i = 0; i < 27; ++i)
+            if (cx[i] == dx && cy[i] == dy && cz[i] == dz) return i;
+        return -1;
+    }
+};
+
+// compile-time loop: f(std::integral_constant<int, I>) for I = 0..N-1
+template <class F, int... Is>
+__host__ __device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, Is...>)
+{
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, class F>
+__host__ __device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// ---------------------------------------------------------------- parameters
+// Single-precision coefficients derived once on the host from cac_params.
+struct DevParams {
+    float rho_g, drho;       // rho = rho_g + drho * phi
+    float mu_g, dmu;         // dynamic viscosity mu = mu_g + dmu * phi
+    float beta4, kappa_phi;  // 4 beta and kappa_phi of the chemical potential
+    float D, kappa;          // CAC diffusivity and compression (kappa = 4 D / delta)
+    float gx, gy, gz;        // body acceleration
+    float eps_phi, eps_n2;   // interface band, squared normal guard
+    float sin_tol, cot_max;
+    int volume_correction;
+    int wall_compression;
+    int variable_density;    // drho != 0: pressure and viscous corrections are live
+};
+
+struct Grid {
+    int nx, ny, nz;
+    uint32_t N, nxny;
+};
+
+// Tiling of the bulk kernels: workgroup = one tile of bx*by*bz nodes.
+struct Tiling {
+    int bx, by, bz;
+    int tx, ty, tz;   // tiles per axis
+    uint32_t ntiles;  // tx*ty*tz
+};
+
+// Device buffers of one lattice (plain handle or one batched domain).
+struct Fields {
+    float *f[2];        // post-collision populations, 27 planes each
+    float *phi[2];      // phase field A/B buffers (fluid values + ghosts)
+    float *u;           // 3 planes
+    float *a;           // compressive flux phi(1-phi)n, 3 planes (fluid: H, wall: W)
+    uint32_t *nbr;      // bit 0: node solid; bit i: node + c_i solid
+    uint8_t *solid;     // 1 = solid
+    int32_t *wall_idx;  // wall-node list (ascending node index)
+    uint8_t *wall_q;    // donor link (255: skipped)
+    float *wall_n;      // unit wall normal, 3 per node
+    float *theta;       // contact angle per wall node
+    double2 *partial;   // per-tile (sum phi*, sum chi)
+    double *scal;       // [0] M_target, [1] lambda, [2] M*, [3] W
+    uint32_t *flag;     // watchdog: nonzero after a non-finite value
+    float *pstar0;      // p* of the initial state (reported before the first step)
+    int nwall;
+};
+
+// ---------------------------------------------------------------- launchers
+// All enqueue on `s`; return the launch status.
+hipError_t launch_ghost(const Grid &g, const DevParams &p, const Fields &F, int cur, hipStream_t s);
+hipError_t launch_hydro(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, int fcur, int pcur,
+                        hipStream_t s);
+hipError_t launch_phase(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, int pcur,
+                        hipStream_t s);
+hipError_t launch_volume(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, int pnext,
+                         hipStream_t s);
+hipError_t launch_init(const Grid &g, const Fields &F, int fcur, const float *u0, const float *ps0,
+                       hipStream_t s);
+hipError_t launch_mass(const Grid &g, const Tiling &t, const Fields &F, const float *phi, double *out,
+                       hipStream_t s);
+hipError_t launch_gather(const Grid &g, const Fields &F, int fcur, int pcur, int stepped, float *phi_out,
+                         float *pstar_out, hipStream_t s);
+
+}  // namespace cac

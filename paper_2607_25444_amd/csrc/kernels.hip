@@ -1,0 +1,711 @@
+// kernels.hip -- gfx950 kernels of the coupled CAC lattice Boltzmann step.
+//
+//   W  k_ghost   ghost-node wetting update (Sec. II B), one thread per wall node
+//   H  k_hydro   fused pull collide-stream of the D3Q27 populations (Sec. II A)
+//   P  k_phase   CAC finite-difference update (Sec. II A 1) + FP64 tile sums
+//   V  k_vol_*   global volume correction (Sec. II C), FP64 reductions
+//
+// Memory layout (structure of arrays, 32-bit node index n = x + nx (y + ny z)):
+//   f[i*N + n]   post-collision populations of the previous step (pull layout)
+//   phi[n]       A/B buffers; fluid values and ghosts share the array
+//   u[d*N + n]   velocity of the last collision, read by the CAC advection
+//   a[d*N + n]   compressive flux phi(1-phi) n, written by H (fluid) and W (wall)
+//   nbr[n]       bit 0: node is solid; bit i: node + c_i is solid
+//
+// Every kernel bounds-checks its node against the grid; bulk kernels map
+// workgroups to tiles so that each XCD works on a contiguous range of tiles.
+#include "cac_internal.hpp"
+
+namespace cac {
+
+// ------------------------------------------------------------------ helpers
+
+// Hardware dispatch sends workgroup b to XCD b % 8.  Re-number so that XCD k
+// owns a contiguous block of logical tiles (halo rows stay in its L2).
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n)
+{
+    const uint32_t k = b & 7u, j = b >> 3, q = n >> 3, r = n & 7u;
+    return k * q + (k < r ? k : r) + j;
+}
+
+struct Node {
+    int x, y, z;
+    bool in;
+};
+
+__device__ __forceinline__ Node tile_node(const Grid &g, const Tiling &t, uint32_t tile)
+{
+    const uint32_t txy = (uint32_t)t.tx * (uint32_t)t.ty;
+    const uint32_t tz = tile / txy;
+    const uint32_t r = tile - tz * txy;
+    const uint32_t ty = r / (uint32_t)t.tx;
+    const uint32_t tx = r - ty * (uint32_t)t.tx;
+    const int tid = threadIdx.x;
+    const int lx = tid % t.bx;
+    const int ly = (tid / t.bx) % t.by;
+    const int lz = tid / (t.bx * t.by);
+    Node nd;
+    nd.x = (int)tx * t.bx + lx;
+    nd.y = (int)ty * t.by + ly;
+    nd.z = (int)tz * t.bz + lz;
+    nd.in = nd.x < g.nx && nd.y < g.ny && nd.z < g.nz;
+    return nd;
+}
+
+// Periodic neighbour offsets along each axis: o[0] = coordinate - 1,
+// o[1] = coordinate, o[2] = coordinate + 1 (wrapped), already scaled by the
+// axis stride.
+struct Offs {
+    uint32_t x[3], y[3], z[3];
+};
+
+__device__ __forceinline__ Offs node_offsets(const Grid &g, int x, int y, int z)
+{
+    Offs o;
+    o.x[0] = (uint32_t)(x ? x - 1 : g.nx - 1);
+    o.x[1] = (uint32_t)x;
+    o.x[2] = (uint32_t)(x + 1 < g.nx ? x + 1 : 0);
+    o.y[0] = (uint32_t)(y ? y - 1 : g.ny - 1) * (uint32_t)g.nx;
+    o.y[1] = (uint32_t)y * (uint32_t)g.nx;
+    o.y[2] = (uint32_t)(y + 1 < g.ny ? y + 1 : 0) * (uint32_t)g.nx;
+    o.z[0] = (uint32_t)(z ? z - 1 : g.nz - 1) * g.nxny;
+    o.z[1] = (uint32_t)z * g.nxny;
+    o.z[2] = (uint32_t)(z + 1 < g.nz ? z + 1 : 0) * g.nxny;
+    return o;
+}
+
+template <int DX, int DY, int DZ>
+__device__ __forceinline__ uint32_t at(const Offs &o)
+{
+    return o.x[DX + 1] + o.y[DY + 1] + o.z[DZ + 1];
+}
+
+// 1-D smoothing weights of the D3Q27 tensor-product weights: w_i = t(cx)t(cy)t(cz)/216,
+// t(0) = 4, t(+-1) = 1.
+__host__ __device__ constexpr float tw(int d) { return d == 0 ? 4.0f : 1.0f; }
+
+// Isotropic gradient (Eq. (22)) and Laplacian (Eq. (23)) from a 3x3x3 stencil
+// s[k], k = (dz+1)*9 + (dy+1)*3 + (dx+1), in tensor-product form on the
+// differences d = s - s(0,0,0) (exact in FP32 for neighbouring values, so the
+// Laplacian does not lose digits to cancellation):
+//   grad_x = sum_{dy,dz} t(dy) t(dz) [d(+1,dy,dz) - d(-1,dy,dz)] / 72
+//   lap    = sum t(dx) t(dy) t(dz) d / 36
+__device__ __forceinline__ void stencil_grad_lap(const float (&s)[27], float &gx, float &gy, float &gz, float &lap)
+{
+    const float c0 = s[13];
+    float S[9];  // x-smoothed differences at (dy, dz)
+    gx = 0.f;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        const float m = s[3 * j] - c0, c = s[3 * j + 1] - c0, p = s[3 * j + 2] - c0;
+        S[j] = m + 4.0f * c + p;
+        const int dy = j % 3 - 1, dz = j / 3 - 1;
+        gx += tw(dy) * tw(dz) * (p - m);
+    }
+    gx *= (1.0f / 72.0f);
+    gy = 0.f;
+    gz = 0.f;
+    float l = 0.f;
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz) gy += tw(dz - 1) * (S[dz * 3 + 2] - S[dz * 3 + 0]);
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) gz += tw(dy - 1) * (S[6 + dy] - S[0 + dy]);
+#pragma unroll
+    for (int j = 0; j < 9; ++j) l += tw(j % 3 - 1) * tw(j / 3 - 1) * S[j];
+    gy *= (1.0f / 72.0f);
+    gz *= (1.0f / 72.0f);
+    lap = l * (1.0f / 36.0f);
+}
+
+// Hermite coefficients of a population set f_i = w_i [ps + 3 c.b + 4.5 H2:C2 + 4.5 H3:C3]
+// (c_s^2 = 1/3).  C3 is symmetric; only the 7 components that D3Q27 carries
+// (H3_aaa = 0 on the lattice) are stored.
+struct Herm {
+    float ps, bx, by, bz;
+    float xx, yy, zz, xy, xz, yz, tr3;  // C2 and trace(C2)/3
+    float xxy, xxz, yyx, yyz, zzx, zzy, xyz;
+};
+
+// Even and odd parts of f_i for the pair (i, opp(i)): f_i = E + O, f_opp = E - O.
+template <int I>
+__device__ __forceinline__ void herm_pair(const Herm &h, float &E, float &O)
+{
+    constexpr float cx = (float)Lat::cx[I], cy = (float)Lat::cy[I], cz = (float)Lat::cz[I];
+    constexpr float w = Lat::w(I);
+    const float ccc = cx * cx * h.xx + cy * cy * h.yy + cz * cz * h.zz +
+                      2.0f * (cx * cy * h.xy + cx * cz * h.xz + cy * cz * h.yz);
+    E = w * (h.ps + 4.5f * (ccc - h.tr3));
+    const float cb = cx * h.bx + cy * h.by + cz * h.bz;
+    constexpr float hx = cx * cx - 1.0f / 3.0f, hy = cy * cy - 1.0f / 3.0f, hz = cz * cz - 1.0f / 3.0f;
+    const float h3 = 3.0f * (hx * (cy * h.xxy + cz * h.xxz) + hy * (cx * h.yyx + cz * h.yyz) +
+                             hz * (cx * h.zzx + cy * h.zzy)) +
+                     6.0f * cx * cy * cz * h.xyz;
+    O = w * (3.0f * cb + 4.5f * h3);
+}
+
+// Single equilibrium population, Eq. (11): w [ps + 3 cu + 4.5 ((cu)^2 - u^2/3) + 4.5 ((cu)^3 - cu u^2)]
+template <int I>
+__device__ __forceinline__ float feq_one(float ps, float ux, float uy, float uz)
+{
+    constexpr float cx = (float)Lat::cx[I], cy = (float)Lat::cy[I], cz = (float)Lat::cz[I];
+    const float cu = cx * ux + cy * uy + cz * uz;
+    const float uu = ux * ux + uy * uy + uz * uz;
+    return Lat::w(I) * (ps + 3.0f * cu + 4.5f * (cu * cu - uu * (1.0f / 3.0f)) + 4.5f * (cu * cu * cu - cu * uu));
+}
+
+// ------------------------------------------------------------------ W: ghosts
+
+// One thread per wall node b (Sec. II B, the ghost-node update):
+//   donor x_f = b + c_q*, phi_f and the isotropic gradient at x_f (fluid
+//   stencil points from the current buffer, wall points from the previous
+//   ghosts in the other buffer: Jacobi), tangential gradient (Eq. (42)),
+//   theta_c = pi - theta (Eq. (43)), normal derivative (Eq. (44)), corrected
+//   gradient (Eq. (45)), lambda_s (Eq. (47)), ghost (Eq. (46)) written to the
+//   current buffer.  Reads only fluid data and old ghosts, writes only b.
+__global__ __launch_bounds__(256) void k_ghost(Grid g, DevParams p, const int32_t *__restrict__ widx,
+                                               const uint8_t *__restrict__ wq, const float *__restrict__ wn,
+                                               const float *__restrict__ theta, int nwall, float *phi_cur,
+                                               const float *__restrict__ phi_old, const uint32_t *__restrict__ nbr,
+                                               float *__restrict__ a)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nwall) return;
+    const int q = wq[k];
+    if (q >= 27) return;  // skipped node: ghost keeps its value
+    const uint32_t b = (uint32_t)widx[k];
+    const int bx = (int)(b % (uint32_t)g.nx);
+    const int by = (int)((b / (uint32_t)g.nx) % (uint32_t)g.ny);
+    const int bz = (int)(b / g.nxny);
+    int cxq = 0, cyq = 0, czq = 0;
+    static_for<27>([&](auto I) {
+        if (q == I) {
+            cxq = Lat::cx[I];
+            cyq = Lat::cy[I];
+            czq = Lat::cz[I];
+        }
+    });
+    int fx = bx + cxq, fy = by + cyq, fz = bz + czq;
+    fx = fx < 0 ? fx + g.nx : (fx >= g.nx ? fx - g.nx : fx);
+    fy = fy < 0 ? fy + g.ny : (fy >= g.ny ? fy - g.ny : fy);
+    fz = fz < 0 ? fz + g.nz : (fz >= g.nz ? fz - g.nz : fz);
+    const Offs o = node_offsets(g, fx, fy, fz);
+    const uint32_t m = nbr[at<0, 0, 0>(o)];
+    float s[27];
+    static_for<27>([&](auto K) {
+        constexpr int kk = K;
+        constexpr int dx = kk % 3 - 1, dy = (kk / 3) % 3 - 1, dz = kk / 9 - 1;
+        constexpr int li = Lat::idx(dx, dy, dz);
+        const uint32_t id = at<dx, dy, dz>(o);
+        s[kk] = ((m >> li) & 1u) ? phi_old[id] : phi_cur[id];
+    });
+    float gx, gy, gz, lap;
+    stencil_grad_lap(s, gx, gy, gz, lap);
+    const float phif = s[13];
+    const float nx = wn[3 * k], ny = wn[3 * k + 1], nz = wn[3 * k + 2];
+    const float gn = gx * nx + gy * ny + gz * nz;
+    const float px = gx - gn * nx, py = gy - gn * ny, pz = gz - gn * nz;
+    const float t = sqrtf(px * px + py * py + pz * pz);
+    const float thc = 3.14159265358979f - theta[k];
+    float sn, cs;
+    sincosf(thc, &sn, &cs);
+    const float cot = (fabsf(sn) < p.sin_tol) ? copysignf(p.cot_max, cs) : cs / sn;
+    const float dn = -t * cot;
+    const float cgx = px + dn * nx, cgy = py + dn * ny, cgz = pz + dn * nz;
+    const float l2 = 4.0f * phif * (1.0f - phif);
+    const float lam = sqrtf(l2 > 0.0f ? l2 : 0.0f);
+    const float gv = phif - lam * (cgx * (float)cxq + cgy * (float)cyq + cgz * (float)czq);
+    phi_cur[b] = gv;
+    if (p.wall_compression) {
+        const float c2 = cgx * cgx + cgy * cgy + cgz * cgz;
+        float ax = 0.f, ay = 0.f, az = 0.f;
+        if (c2 > p.eps_n2) {
+            const float sc = gv * (1.0f - gv) * rsqrtf(c2);
+            ax = sc * cgx;
+            ay = sc * cgy;
+            az = sc * cgz;
+        }
+        a[b] = ax;
+        a[g.N + b] = ay;
+        a[2u * g.N + b] = az;
+    }
+}
+
+// ------------------------------------------------------------------ H: hydro
+
+// Fused pull collide-stream at fluid node x (Sec. II A):
+//   pull f_i(x) = f*_i(x - c_i), or f*_opp(i)(x) when x - c_i is solid
+//   (halfway bounce-back); phi stencil -> grad, lap (Eqs. (22)-(23));
+//   mu_phi and F_sigma (Eq. (19)); mixture laws (Eqs. (8)-(10)); moments
+//   (Eqs. (6)-(7)); F_p (Eq. (20)), F_ext, F_nu (Eq. (21)); third-order
+//   equilibrium (Eq. (11)), Guo forcing (Eq. (17)) with the trapezoidal shift,
+//   recursive regularisation (Eqs. (14), (16)):
+//     f*_i = w_i [p* + 3 c.(u + a/2) + 4.5 H2:C2 + 4.5 H3:C3],
+//     C2 = uu + (ua + au)/2 + (1 - omega) A2,  C3 = uuu + (1 - omega) S(u A2),
+//     A2 = P - p*/3 I - uu + (ua + au)/2  (second moment of f - f^eq + S/2).
+//   Writes f*, u and the compressive flux a = phi(1-phi) grad/|grad|.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_hydro(Grid g, Tiling t, DevParams p, const float *__restrict__ fin,
+                                              float *__restrict__ fout, const float *__restrict__ phi,
+                                              const uint32_t *__restrict__ nbr, float *__restrict__ u,
+                                              float *__restrict__ a, uint32_t *__restrict__ flag)
+{
+    const Node nd = tile_node(g, t, xcd_tile(blockIdx.x, t.ntiles));
+    if (!nd.in) return;
+    const Offs o = node_offsets(g, nd.x, nd.y, nd.z);
+    const uint32_t n = at<0, 0, 0>(o);
+    const uint32_t m = nbr[n];
+    if (m & 1u) return;
+    const uint32_t N = g.N;
+
+    float s[27];
+    static_for<27>([&](auto K) {
+        constexpr int kk = K;
+        s[kk] = phi[at<kk % 3 - 1, (kk / 3) % 3 - 1, kk / 9 - 1>(o)];
+    });
+    float f[27];
+    static_for<27>([&](auto I) {
+        constexpr int i = I;
+        if constexpr (i == 0) {
+            f[0] = fin[n];
+        } else {
+            constexpr int ob = Lat::opp(i);
+            const uint32_t src = at<Lat::cx[ob], Lat::cy[ob], Lat::cz[ob]>(o);  // x - c_i
+            const bool wall = (m >> ob) & 1u;
+            f[i] = fin[wall ? (uint32_t)ob * N + n : (uint32_t)i * N + src];
+        }
+    });
+
+    float gx, gy, gz, lap;
+    stencil_grad_lap(s, gx, gy, gz, lap);
+    const float ph = s[13];
+
+    // kinetic moments
+    float ps = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+    float Pxx = 0.f, Pyy = 0.f, Pzz = 0.f, Pxy = 0.f, Pxz = 0.f, Pyz = 0.f;
+    static_for<27>([&](auto I) {
+        constexpr int i = I;
+        constexpr float cx = (float)Lat::cx[i], cy = (float)Lat::cy[i], cz = (float)Lat::cz[i];
+        const float v = f[i];
+        ps += v;
+        if constexpr (Lat::cx[i] != 0) { jx += cx * v; Pxx += v; }
+        if constexpr (Lat::cy[i] != 0) { jy += cy * v; Pyy += v; }
+        if constexpr (Lat::cz[i] != 0) { jz += cz * v; Pzz += v; }
+        if constexpr (Lat::cx[i] * Lat::cy[i] != 0) Pxy += cx * cy * v;
+        if constexpr (Lat::cx[i] * Lat::cz[i] != 0) Pxz += cx * cz * v;
+        if constexpr (Lat::cy[i] * Lat::cz[i] != 0) Pyz += cy * cz * v;
+    });
+
+    // chemical potential, capillary force, mixture properties
+    const float mu_phi = p.beta4 * ph * (ph - 1.0f) * (ph - 0.5f) - p.kappa_phi * lap;
+    float Fx = mu_phi * gx, Fy = mu_phi * gy, Fz = mu_phi * gz;
+    const float rho = p.rho_g + p.drho * ph;
+    const float irho = 1.0f / rho;
+    const float nu = (p.mu_g + p.dmu * ph) * irho;
+    const float omega = 1.0f / (0.5f + 3.0f * nu);
+    float ax, ay, az;
+    if (p.variable_density) {
+        const float grx = p.drho * gx, gry = p.drho * gy, grz = p.drho * gz;
+        const float cp = -ps * (1.0f / 3.0f);
+        const float fe = p.drho * ph;
+        Fx += cp * grx + fe * p.gx;
+        Fy += cp * gry + fe * p.gy;
+        Fz += cp * grz + fe * p.gz;
+        const float a1x = Fx * irho, a1y = Fy * irho, a1z = Fz * irho;
+        const float ux1 = jx + 0.5f * a1x, uy1 = jy + 0.5f * a1y, uz1 = jz + 0.5f * a1z;
+        const float p3 = ps * (1.0f / 3.0f);
+        const float Qxx = Pxx - p3 - ux1 * ux1, Qyy = Pyy - p3 - uy1 * uy1, Qzz = Pzz - p3 - uz1 * uz1;
+        const float Qxy = Pxy - ux1 * uy1, Qxz = Pxz - ux1 * uz1, Qyz = Pyz - uy1 * uz1;
+        const float cnu = -3.0f * nu * omega * irho;
+        ax = a1x + cnu * (Qxx * grx + Qxy * gry + Qxz * grz);
+        ay = a1y + cnu * (Qxy * grx + Qyy * gry + Qyz * grz);
+        az = a1z + cnu * (Qxz * grx + Qyz * gry + Qzz * grz);
+    } else {
+        ax = Fx * irho;
+        ay = Fy * irho;
+        az = Fz * irho;
+    }
+    const float ux = jx + 0.5f * ax, uy = jy + 0.5f * ay, uz = jz + 0.5f * az;
+
+    // A2 (R2 reading: local second moment of f - f^eq + S/2)
+    const float p3 = ps * (1.0f / 3.0f);
+    const float A2xx = Pxx - p3 - ux * ux + ux * ax;
+    const float A2yy = Pyy - p3 - uy * uy + uy * ay;
+    const float A2zz = Pzz - p3 - uz * uz + uz * az;
+    const float A2xy = Pxy - ux * uy + 0.5f * (ux * ay + ax * uy);
+    const float A2xz = Pxz - ux * uz + 0.5f * (ux * az + ax * uz);
+    const float A2yz = Pyz - uy * uz + 0.5f * (uy * az + ay * uz);
+    const float om1 = 1.0f - omega;
+
+    Herm h;
+    h.ps = ps;
+    h.bx = ux + 0.5f * ax;
+    h.by = uy + 0.5f * ay;
+    h.bz = uz + 0.5f * az;
+    h.xx = ux * ux + ux * ax + om1 * A2xx;
+    h.yy = uy * uy + uy * ay + om1 * A2yy;
+    h.zz = uz * uz + uz * az + om1 * A2zz;
+    h.xy = ux * uy + 0.5f * (ux * ay + ax * uy) + om1 * A2xy;
+    h.xz = ux * uz + 0.5f * (ux * az + ax * uz) + om1 * A2xz;
+    h.yz = uy * uz + 0.5f * (uy * az + ay * uz) + om1 * A2yz;
+    h.tr3 = (h.xx + h.yy + h.zz) * (1.0f / 3.0f);
+    // C3 = uuu + (1 - omega)(u_a A2_bg + u_b A2_ag + u_g A2_ab)
+    h.xxy = ux * ux * uy + om1 * (2.0f * ux * A2xy + uy * A2xx);
+    h.xxz = ux * ux * uz + om1 * (2.0f * ux * A2xz + uz * A2xx);
+    h.yyx = uy * uy * ux + om1 * (2.0f * uy * A2xy + ux * A2yy);
+    h.yyz = uy * uy * uz + om1 * (2.0f * uy * A2yz + uz * A2yy);
+    h.zzx = uz * uz * ux + om1 * (2.0f * uz * A2xz + ux * A2zz);
+    h.zzy = uz * uz * uy + om1 * (2.0f * uz * A2yz + uy * A2zz);
+    h.xyz = ux * uy * uz + om1 * (ux * A2yz + uy * A2xz + uz * A2xy);
+
+    fout[n] = Lat::w(0) * (h.ps - 4.5f * h.tr3);
+    static_for<13>([&](auto P) {
+        constexpr int i = 2 * P + 1;
+        float E, O;
+        herm_pair<i>(h, E, O);
+        fout[(uint32_t)i * N + n] = E + O;
+        fout[(uint32_t)(i + 1) * N + n] = E - O;
+    });
+
+    u[n] = ux;
+    u[N + n] = uy;
+    u[2u * N + n] = uz;
+    const float g2 = gx * gx + gy * gy + gz * gz;
+    float cx = 0.f, cy = 0.f, cz = 0.f;
+    if (g2 > p.eps_n2) {
+        const float sc = ph * (1.0f - ph) * rsqrtf(g2);
+        cx = sc * gx;
+        cy = sc * gy;
+        cz = sc * gz;
+    }
+    a[n] = cx;
+    a[N + n] = cy;
+    a[2u * N + n] = cz;
+    if (!(isfinite(ux) && isfinite(uy) && isfinite(uz) && isfinite(ps))) flag[0] = 1u;
+}
+
+// ------------------------------------------------------------------ P: CAC
+
+__device__ __forceinline__ float minmod(float a, float b)
+{
+    // Eq. (32)
+    return (a * b <= 0.0f) ? 0.0f : (a > 0.0f ? fminf(a, b) : fmaxf(a, b));
+}
+
+// Face flux between nodes L and R (R = L + e_d), Eqs. (30)-(34):
+// u_f = (u_L + u_R)/2, minmod slopes at L and R, upwind reconstruction.
+__device__ __forceinline__ float muscl_flux(float pLL, float pL, float pR, float pRR, float uL, float uR)
+{
+    const float uf = 0.5f * (uL + uR);
+    const float sL = minmod(pL - pLL, pR - pL);
+    const float sR = minmod(pR - pL, pRR - pR);
+    return uf * (uf >= 0.0f ? pL + 0.5f * sL : pR - 0.5f * sR);
+}
+
+template <int NT>
+__device__ __forceinline__ void block_sum2(double &x, double &y)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        x += __shfl_xor(x, off, 64);
+        y += __shfl_xor(y, off, 64);
+    }
+    __shared__ double sx[NT / 64], sy[NT / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        sx[wid] = x;
+        sy[wid] = y;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tx = 0.0, ty = 0.0;
+#pragma unroll
+        for (int k = 0; k < NT / 64; ++k) {
+            tx += sx[k];
+            ty += sy[k];
+        }
+        x = tx;
+        y = ty;
+    }
+}
+
+// CAC update at fluid node x (Eq. (28)):
+//   phi* = phi - div(F_a) + D lap(phi) - kappa div_iso(a)
+// F_a from the MUSCL-minmod face fluxes, zero on faces touching a solid node;
+// div_iso with the weights w_i/c_s^2 (tensor-product form).  Also accumulates
+// sum(phi*) and sum(chi), chi = phi*(1-phi*) inside the band (Eqs. (49), (51)),
+// in FP64 per tile.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_phase(Grid g, Tiling t, DevParams p, const float *__restrict__ phi,
+                                              float *__restrict__ phi_out, const float *__restrict__ u,
+                                              const float *__restrict__ a, const uint32_t *__restrict__ nbr,
+                                              double2 *__restrict__ partial, uint32_t *__restrict__ flag)
+{
+    const uint32_t tile = xcd_tile(blockIdx.x, t.ntiles);
+    const Node nd = tile_node(g, t, tile);
+    double sphi = 0.0, schi = 0.0;
+    if (nd.in) {
+        const Offs o = node_offsets(g, nd.x, nd.y, nd.z);
+        const uint32_t n = at<0, 0, 0>(o);
+        const uint32_t m = nbr[n];
+        if (!(m & 1u)) {
+            const uint32_t N = g.N;
+            float s[27];
+            static_for<27>([&](auto K) {
+                constexpr int kk = K;
+                s[kk] = phi[at<kk % 3 - 1, (kk / 3) % 3 - 1, kk / 9 - 1>(o)];
+            });
+            float gx, gy, gz, lap;
+            stencil_grad_lap(s, gx, gy, gz, lap);
+            const float ph = s[13];
+            // second neighbours along the axes (wrapped)
+            const int x2m = nd.x >= 2 ? nd.x - 2 : nd.x - 2 + g.nx, x2p = nd.x + 2 < g.nx ? nd.x + 2 : nd.x + 2 - g.nx;
+            const int y2m = nd.y >= 2 ? nd.y - 2 : nd.y - 2 + g.ny, y2p = nd.y + 2 < g.ny ? nd.y + 2 : nd.y + 2 - g.ny;
+            const int z2m = nd.z >= 2 ? nd.z - 2 : nd.z - 2 + g.nz, z2p = nd.z + 2 < g.nz ? nd.z + 2 : nd.z + 2 - g.nz;
+            const uint32_t yz = o.y[1] + o.z[1], xz = o.x[1] + o.z[1], xy = o.x[1] + o.y[1];
+            float div_a = 0.0f;
+            {  // x faces
+                const float umid = u[n];
+                const float pm2 = phi[(uint32_t)x2m + yz], pp2 = phi[(uint32_t)x2p + yz];
+                const float pm = s[12], pp = s[14];
+                if (!((m >> 1) & 1u)) div_a += muscl_flux(pm, ph, pp, pp2, umid, u[o.x[2] + yz]);
+                if (!((m >> 2) & 1u)) div_a -= muscl_flux(pm2, pm, ph, pp, u[o.x[0] + yz], umid);
+            }
+            {  // y faces
+                const float umid = u[N + n];
+                const float pm2 = phi[(uint32_t)y2m * (uint32_t)g.nx + xz];
+                const float pp2 = phi[(uint32_t)y2p * (uint32_t)g.nx + xz];
+                const float pm = s[10], pp = s[16];
+                if (!((m >> 3) & 1u)) div_a += muscl_flux(pm, ph, pp, pp2, umid, u[N + o.y[2] + xz]);
+                if (!((m >> 4) & 1u)) div_a -= muscl_flux(pm2, pm, ph, pp, u[N + o.y[0] + xz], umid);
+            }
+            {  // z faces
+                const float umid = u[2u * N + n];
+                const float pm2 = phi[(uint32_t)z2m * g.nxny + xy];
+                const float pp2 = phi[(uint32_t)z2p * g.nxny + xy];
+                const float pm = s[4], pp = s[22];
+                if (!((m >> 5) & 1u)) div_a += muscl_flux(pm, ph, pp, pp2, umid, u[2u * N + o.z[2] + xy]);
+                if (!((m >> 6) & 1u)) div_a -= muscl_flux(pm2, pm, ph, pp, u[2u * N + o.z[0] + xy], umid);
+            }
+            // isotropic divergence of the compressive flux (a = 0 on solid nodes
+            // unless the ghost update assigned one)
+            float dx = 0.f, dy = 0.f, dz = 0.f;
+            static_for<9>([&](auto J) {
+                constexpr int j = J;
+                constexpr int e1 = j % 3 - 1, e2 = j / 3 - 1;
+                constexpr float wgt = tw(e1) * tw(e2);
+                dx += wgt * (a[at<1, e1, e2>(o)] - a[at<-1, e1, e2>(o)]);
+                dy += wgt * (a[N + at<e1, 1, e2>(o)] - a[N + at<e1, -1, e2>(o)]);
+                dz += wgt * (a[2u * N + at<e1, e2, 1>(o)] - a[2u * N + at<e1, e2, -1>(o)]);
+            });
+            const float div_c = (dx + dy + dz) * (1.0f / 72.0f);
+            const float ps = ph - div_a + p.D * lap - p.kappa * div_c;
+            phi_out[n] = ps;
+            if (!isfinite(ps)) flag[0] = 1u;
+            sphi = (double)ps;
+            schi = (ps > p.eps_phi && ps < 1.0f - p.eps_phi) ? (double)ps * (1.0 - (double)ps) : 0.0;
+        }
+    }
+    block_sum2<NT>(sphi, schi);
+    if (threadIdx.x == 0) partial[tile] = make_double2(sphi, schi);
+}
+
+// ------------------------------------------------------------------ V: volume
+
+// Sum of the per-tile partials in a fixed order (deterministic), then
+// lambda = (M_target - M*) / W when W > 0 (Eqs. (49)-(55)).
+__global__ __launch_bounds__(1024) void k_vol_finalize(const double2 *__restrict__ partial, uint32_t np,
+                                                       double *__restrict__ scal, int vc)
+{
+    double x = 0.0, y = 0.0;
+    for (uint32_t k = threadIdx.x; k < np; k += 1024) {
+        const double2 v = partial[k];
+        x += v.x;
+        y += v.y;
+    }
+    block_sum2<1024>(x, y);
+    if (threadIdx.x == 0) {
+        const double lam = (vc && y > 0.0) ? (scal[0] - x) / y : 0.0;
+        scal[1] = lam;
+        scal[2] = x;
+        scal[3] = y;
+    }
+}
+
+// phi^{n+1} = phi* + lambda chi(phi*) on fluid nodes (Eq. (53)).
+__global__ __launch_bounds__(256) void k_vol_apply(uint32_t N, const uint8_t *__restrict__ solid,
+                                                   float *__restrict__ phi, const double *__restrict__ scal,
+                                                   float eps_phi)
+{
+    const uint32_t n = blockIdx.x * 256u + threadIdx.x;
+    if (n >= N || solid[n]) return;
+    const double lam = scal[1];
+    const float v = phi[n];
+    if (v > eps_phi && v < 1.0f - eps_phi) phi[n] = (float)((double)v + lam * ((double)v * (1.0 - (double)v)));
+}
+
+// ------------------------------------------------------------------ init, mass, gather
+
+// Populations that stream into f^eq(p*0, u0): f*_j(y) = f^eq_j(x) at x = y + c_j
+// when x is fluid, else f^eq_opp(j)(y) (the inverse of the pull with bounce-back).
+__global__ __launch_bounds__(256) void k_init(Grid g, float *__restrict__ f, const uint32_t *__restrict__ nbr,
+                                              const float *__restrict__ u0, const float *__restrict__ ps0)
+{
+    const uint32_t n = blockIdx.x * 256u + threadIdx.x;
+    if (n >= g.N) return;
+    const uint32_t m = nbr[n];
+    if (m & 1u) return;
+    const int x = (int)(n % (uint32_t)g.nx), y = (int)((n / (uint32_t)g.nx) % (uint32_t)g.ny), z = (int)(n / g.nxny);
+    const Offs o = node_offsets(g, x, y, z);
+    auto ld = [&](uint32_t id, float &ps, float &ux, float &uy, float &uz) {
+        ps = ps0 ? ps0[id] : 0.f;
+        ux = u0 ? u0[id] : 0.f;
+        uy = u0 ? u0[g.N + id] : 0.f;
+        uz = u0 ? u0[2u * g.N + id] : 0.f;
+    };
+    float ps, ux, uy, uz;
+    ld(n, ps, ux, uy, uz);
+    f[n] = feq_one<0>(ps, ux, uy, uz);
+    static_for<26>([&](auto J) {
+        constexpr int j = J + 1;
+        constexpr int oj = Lat::opp(j);
+        if ((m >> j) & 1u) {
+            f[(uint32_t)j * g.N + n] = feq_one<oj>(ps, ux, uy, uz);
+        } else {
+            float ps2, ux2, uy2, uz2;
+            ld(at<Lat::cx[j], Lat::cy[j], Lat::cz[j]>(o), ps2, ux2, uy2, uz2);
+            f[(uint32_t)j * g.N + n] = feq_one<j>(ps2, ux2, uy2, uz2);
+        }
+    });
+}
+
+// Per-block FP64 sums of phi over fluid nodes.
+__global__ __launch_bounds__(256) void k_mass_partial(uint32_t N, const uint8_t *__restrict__ solid,
+                                                      const float *__restrict__ phi, double2 *__restrict__ partial)
+{
+    const uint32_t n = blockIdx.x * 256u + threadIdx.x;
+    double x = 0.0, y = 0.0;
+    if (n < N && !solid[n]) x = (double)phi[n];
+    block_sum2<256>(x, y);
+    if (threadIdx.x == 0) partial[blockIdx.x] = make_double2(x, y);
+}
+
+__global__ __launch_bounds__(1024) void k_mass_final(const double2 *__restrict__ partial, uint32_t np,
+                                                     double *__restrict__ out)
+{
+    double x = 0.0, y = 0.0;
+    for (uint32_t k = threadIdx.x; k < np; k += 1024) x += partial[k].x;
+    block_sum2<1024>(x, y);
+    if (threadIdx.x == 0) out[0] = x;
+}
+
+// Fields for output: phi from the current buffer on fluid nodes and from the
+// buffer holding the latest ghosts on solid nodes; p* as the zeroth moment of
+// the post-collision populations (equal to p* of the last collision).
+__global__ __launch_bounds__(256) void k_gather(uint32_t N, const uint8_t *__restrict__ solid,
+                                                const float *__restrict__ phi_fluid,
+                                                const float *__restrict__ phi_ghost, const float *__restrict__ f,
+                                                const float *__restrict__ pstar0, int stepped,
+                                                float *__restrict__ phi_out, float *__restrict__ ps_out)
+{
+    const uint32_t n = blockIdx.x * 256u + threadIdx.x;
+    if (n >= N) return;
+    const bool sol = solid[n] != 0;
+    if (phi_out) phi_out[n] = sol ? phi_ghost[n] : phi_fluid[n];
+    if (ps_out) {
+        float v = 0.f;
+        if (!stepped) {
+            v = pstar0[n];
+        } else if (!sol) {
+#pragma unroll
+            for (int i = 0; i < 27; ++i) v += f[(uint32_t)i * N + n];
+        }
+        ps_out[n] = v;
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline unsigned blocks_for(uint32_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t launch_ghost(const Grid &g, const DevParams &p, const Fields &F, int cur, hipStream_t s)
+{
+    if (F.nwall == 0) return hipSuccess;
+    k_ghost<<<blocks_for((uint32_t)F.nwall, 256), 256, 0, s>>>(g, p, F.wall_idx, F.wall_q, F.wall_n, F.theta,
+                                                                F.nwall, F.phi[cur], F.phi[cur ^ 1], F.nbr, F.a);
+    return hipGetLastError();
+}
+
+hipError_t launch_hydro(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, int fcur, int pcur,
+                        hipStream_t s)
+{
+    const int nt = t.bx * t.by * t.bz;
+    switch (nt) {
+    case 128:
+        k_hydro<128><<<t.ntiles, 128, 0, s>>>(g, t, p, F.f[fcur], F.f[fcur ^ 1], F.phi[pcur], F.nbr, F.u, F.a, F.flag);
+        break;
+    case 256:
+        k_hydro<256><<<t.ntiles, 256, 0, s>>>(g, t, p, F.f[fcur], F.f[fcur ^ 1], F.phi[pcur], F.nbr, F.u, F.a, F.flag);
+        break;
+    case 512:
+        k_hydro<512><<<t.ntiles, 512, 0, s>>>(g, t, p, F.f[fcur], F.f[fcur ^ 1], F.phi[pcur], F.nbr, F.u, F.a, F.flag);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_phase(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, int pcur,
+                        hipStream_t s)
+{
+    const int nt = t.bx * t.by * t.bz;
+    switch (nt) {
+    case 128:
+        k_phase<128><<<t.ntiles, 128, 0, s>>>(g, t, p, F.phi[pcur], F.phi[pcur ^ 1], F.u, F.a, F.nbr, F.partial, F.flag);
+        break;
+    case 256:
+        k_phase<256><<<t.ntiles, 256, 0, s>>>(g, t, p, F.phi[pcur], F.phi[pcur ^ 1], F.u, F.a, F.nbr, F.partial, F.flag);
+        break;
+    case 512:
+        k_phase<512><<<t.ntiles, 512, 0, s>>>(g, t, p, F.phi[pcur], F.phi[pcur ^ 1], F.u, F.a, F.nbr, F.partial, F.flag);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_volume(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, int pnext,
+                         hipStream_t s)
+{
+    k_vol_finalize<<<1, 1024, 0, s>>>(F.partial, t.ntiles, F.scal, p.volume_correction);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_vol_apply<<<blocks_for(g.N, 256), 256, 0, s>>>(g.N, F.solid, F.phi[pnext], F.scal, p.eps_phi);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const Grid &g, const Fields &F, int fcur, const float *u0, const float *ps0, hipStream_t s)
+{
+    k_init<<<blocks_for(g.N, 256), 256, 0, s>>>(g, F.f[fcur], F.nbr, u0, ps0);
+    return hipGetLastError();
+}
+
+hipError_t launch_mass(const Grid &g, const Tiling &t, const Fields &F, const float *phi, double *out, hipStream_t s)
+{
+    // the partial array holds at least one entry per 256 nodes (sized by the runtime)
+    const unsigned nb = blocks_for(g.N, 256);
+    k_mass_partial<<<nb, 256, 0, s>>>(g.N, F.solid, phi, F.partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_mass_final<<<1, 1024, 0, s>>>(F.partial, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const Grid &g, const Fields &F, int fcur, int pcur, int stepped, float *phi_out,
+                         float *pstar_out, hipStream_t s)
+{
+    k_gather<<<blocks_for(g.N, 256), 256, 0, s>>>(g.N, F.solid, F.phi[pcur], F.phi[pcur ^ 1], F.f[fcur], F.pstar0,
+                                                  stepped, phi_out, pstar_out);
+    return hipGetLastError();
+}
+
+}  // namespace cac

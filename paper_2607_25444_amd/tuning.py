@@ -1,0 +1,21 @@
+"""Launch shapes of the bulk kernels (tile bx * by * bz nodes per workgroup).
+
+``launch_for`` is the configuration the benchmark times and the full-size
+parity test uses; the autotuner in ``bench.py --tune`` searches the same space.
+"""
+from __future__ import annotations
+
+CANDIDATES = [
+    (64, 4, 1), (64, 2, 2), (64, 1, 4), (32, 8, 1), (32, 4, 2), (32, 2, 4), (16, 4, 4),
+    (64, 2, 1), (64, 1, 2), (32, 4, 1), (128, 2, 1), (128, 1, 2), (64, 8, 1), (64, 4, 2), (128, 4, 1),
+]
+
+
+def launch_for(shape):
+    """(bx, by, bz, use_graph) for a lattice of this shape."""
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    bx = 64 if nx >= 64 else (32 if nx >= 32 else 16)
+    by = max(1, min(4, 256 // bx))
+    bz = 256 // (bx * by)
+    return (bx, by, bz, 1 if n <= (1 << 22) else 0)

@@ -1,0 +1,100 @@
+"""Host-only checks of the C ABI library (no GPU use): it loads, exports every
+symbol that include/cac.h declares, validates arguments before touching the
+device, and its host-side wall tables equal the oracle's independent ones."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2607_25444_amd import capi
+from paper_2607_25444_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "cac.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cac_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return capi.load_library()
+
+
+def test_exports_every_declared_symbol(lib):
+    syms = _declared_symbols()
+    assert len(syms) >= 15
+    for s in syms:
+        assert hasattr(lib, s), s
+        assert s in capi.SIGNATURES, s
+
+
+def test_status_strings(lib):
+    for st in range(7):
+        assert lib.cac_status_string(st)
+    assert b"unknown" in lib.cac_status_string(99)
+
+
+def test_default_params_match_workloads(lib):
+    p = capi.CacParams()
+    assert lib.cac_default_params(C.byref(p)) == capi.CAC_OK
+    d = W.default_params()
+    for k, v in d.items():
+        if k == "g":
+            assert list(p.g) == list(v)
+        else:
+            assert getattr(p, k) == pytest.approx(v), k
+
+
+def test_init_rejects_bad_arguments(lib):
+    p = capi.CacParams()
+    lib.cac_default_params(C.byref(p))
+    h = C.c_void_p()
+    cb = capi.ALLOC_FN(lambda n, u: 0)
+    assert lib.cac_init(C.byref(h), 0, 4, 4, C.byref(p), cb, None, None) == capi.CAC_ERR_ARG
+    assert lib.cac_init(C.byref(h), 1024, 1024, 1024, C.byref(p), cb, None, None) == capi.CAC_ERR_ARG
+    p.delta = 0.0
+    assert lib.cac_init(C.byref(h), 8, 8, 8, C.byref(p), cb, None, None) == capi.CAC_ERR_ARG
+    assert lib.cac_init(None, 8, 8, 8, C.byref(p), cb, None, None) == capi.CAC_ERR_ARG
+    assert not h.value
+    assert lib.cac_step(None, 1) == capi.CAC_ERR_ARG
+    assert lib.cac_volume(None, None) == capi.CAC_ERR_ARG
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    saved = capi._lib
+    try:
+        capi._lib = None
+        with pytest.raises(ImportError):
+            capi.load_library(str(tmp_path / "nope.so"))
+    finally:
+        capi._lib = saved
+
+
+@pytest.mark.parametrize("case", ["flat", "random0", "random1", "random2", "orifice", "block"])
+def test_wall_tables_equal_oracle(orc, case):
+    """Wall list, six-times normal and donor link: library host code and the
+    oracle's own implementation agree exactly."""
+    if case == "flat":
+        shape = (9, 7, 6)
+        solid = W.flat_walls(shape)
+    elif case.startswith("random"):
+        shape = (14, 12, 12)
+        solid = W.random_geometry(shape, int(case[-1]), n_blocks=5)
+    elif case == "orifice":
+        shape = (24, 24, 20)
+        solid = W.orifice_plate_mask(shape, 8, 3, 10.0)
+    else:
+        shape = (12, 12, 12)
+        z, y, x = np.meshgrid(np.arange(12), np.arange(12), np.arange(12), indexing="ij")
+        solid = ((abs(x - 5.5) < 3) & (abs(y - 5.5) < 3) & (abs(z - 5.5) < 3)).astype(np.uint8).reshape(-1)
+    i1, n1, q1 = capi.wall_tables(solid, shape)
+    i2, n2, q2 = orc.wall_nodes(solid, shape)
+    np.testing.assert_array_equal(i1, i2)
+    np.testing.assert_array_equal(n1, n2)
+    np.testing.assert_array_equal(q1, q2)
+    assert len(i1) > 0

@@ -1,0 +1,176 @@
+"""GPU (FP32, libcac through its C ABI) against the FP64 oracle.
+
+Tolerances: after one step every field within 2e-6 absolute (phi) or 1e-5 of
+its maximum (u, p*, populations); after 200 steps of the 32^3 sessile
+droplet max |phi_gpu - phi_oracle| <= 1e-5 and max |u_gpu - u_oracle| <=
+1e-4 max |u_oracle| over fluid nodes.  Both sides start from the same FP32
+inputs (the oracle widens them to FP64)."""
+import numpy as np
+import pytest
+
+from paper_2607_25444_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+Q = 27
+
+
+def _params(w, **kw):
+    p = dict(w.params)
+    p.update(kw)
+    return p
+
+
+def gpu_run(w, steps, launch=None, **kw):
+    from paper_2607_25444_amd import capi
+    s = capi.Sim(w.shape, _params(w, **kw))
+    if launch:
+        s.set_launch(*launch)
+    s.set_geometry(w.solid, w.theta)
+    s.set_state(w.phi0)
+    s.step(steps)
+    phi, u, ps = s.fields()
+    f = s.populations()
+    s.sync()
+    out = dict(phi=phi.cpu().numpy().astype(np.float64), u=u.cpu().numpy().astype(np.float64),
+               pstar=ps.cpu().numpy().astype(np.float64), f=f.cpu().numpy().astype(np.float64),
+               volume=s.volume())
+    s.close()
+    return out
+
+
+def oracle_run(orc, w, steps, **kw):
+    p = orc.Params(**_params(w, **kw))
+    s = orc.OracleSim.create(w.shape, w.solid, w.theta.astype(np.float64), p, w.phi0.astype(np.float64))
+    fpost = np.zeros(Q * w.N)
+    if steps:
+        s.step(steps, fpost=fpost)
+    return dict(phi=s.phi, u=s.u, pstar=s.pstar, f=fpost, M=s.M_target)
+
+
+def _masks(w, orc):
+    fl = w.solid == 0
+    idx, _, _ = orc.wall_nodes(w.solid, w.shape)
+    wall = np.zeros(w.N, bool)
+    wall[idx] = True
+    return fl, wall
+
+
+def _cmp(g, o, w, orc, phi_tol, rel_tol, with_f=True):
+    fl, wall = _masks(w, orc)
+    N = w.N
+    dphi = np.abs(g["phi"] - o["phi"])
+    assert dphi[fl].max() <= phi_tol, f"phi fluid {dphi[fl].max():.3e}"
+    assert dphi[wall].max() <= phi_tol, f"phi ghosts {dphi[wall].max():.3e}"
+    uo, ug = o["u"].reshape(3, N)[:, fl], g["u"].reshape(3, N)[:, fl]
+    assert np.abs(ug - uo).max() <= rel_tol * max(np.abs(uo).max(), 1e-12), \
+        f"u {np.abs(ug - uo).max():.3e} vs max {np.abs(uo).max():.3e}"
+    po, pg = o["pstar"][fl], g["pstar"][fl]
+    assert np.abs(pg - po).max() <= rel_tol * max(np.abs(po).max(), 1e-4), f"p* {np.abs(pg - po).max():.3e}"
+    if with_f:
+        fo, fg = o["f"].reshape(Q, N)[:, fl], g["f"].reshape(Q, N)[:, fl]
+        assert np.abs(fg - fo).max() <= rel_tol * max(np.abs(fo).max(), 1e-6), \
+            f"f {np.abs(fg - fo).max():.3e} vs max {np.abs(fo).max():.3e}"
+
+
+def _variable_density_case(shape=(20, 12, 14), seed=3):
+    solid = W.random_geometry(shape, seed, n_blocks=3)
+    nx, ny, nz = shape
+    phi0 = W.tanh_droplet(shape, (nx / 2, ny / 2, nz / 2), 4.5, 4.0).astype(np.float32)
+    rng = np.random.default_rng(seed)
+    theta = np.deg2rad(rng.uniform(30, 150, size=nx * ny * nz)).astype(np.float32)
+    prm = W.default_params(rho_l=1.2, rho_g=0.9, nu_l=0.031, nu_g=0.24, sigma=0.025, g=(1e-5, -2e-5, -1e-4))
+    return W.Workload("vardens", shape, solid, theta, phi0, prm, 0)
+
+
+@pytest.mark.parametrize("wc", [0, 1])
+def test_one_step_all_fields(orc, wc):
+    """One step on a random voxel geometry with per-node angles, density and
+    viscosity contrast and a body force: every term of the step is live."""
+    w = _variable_density_case()
+    o = oracle_run(orc, w, 1, wall_compression=wc)
+    g = gpu_run(w, 1, wall_compression=wc)
+    _cmp(g, o, w, orc, 2e-6, 1e-5)
+
+
+@pytest.mark.parametrize("steps", [0, 1, 5])
+def test_sessile_initial_steps(orc, steps):
+    w = W.sessile_32(60.0)
+    o = oracle_run(orc, w, steps)
+    g = gpu_run(w, steps)
+    _cmp(g, o, w, orc, 2e-6, 1e-5, with_f=steps > 0)
+
+
+@pytest.mark.parametrize("wc", [1, 0])
+def test_sessile_200_steps(orc, wc):
+    """Static sessile droplet 32^3, theta = 60 deg, 200 steps: phi within 1e-5,
+    u within 1e-4 of max|u| (FP32 against FP64)."""
+    w = W.sessile_32(60.0)
+    o = oracle_run(orc, w, 200, wall_compression=wc)
+    g = gpu_run(w, 200, wall_compression=wc)
+    fl, wall = _masks(w, orc)
+    N = w.N
+    dphi = np.abs(g["phi"] - o["phi"])
+    print("phi err fluid", dphi[fl].max(), "ghost", dphi[wall].max(), flush=True)
+    assert dphi[fl].max() <= 1e-5
+    assert dphi[wall].max() <= 1e-5
+    uo, ug = o["u"].reshape(3, N)[:, fl], g["u"].reshape(3, N)[:, fl]
+    print("u err", np.abs(ug - uo).max(), "max u", np.abs(uo).max())
+    assert np.abs(ug - uo).max() <= 1e-4 * np.abs(uo).max()
+    assert g["volume"] == pytest.approx(o["M"], rel=1e-6)
+
+
+@pytest.mark.parametrize("launch", [None, (16, 4, 4, 0), (32, 2, 4, 1), (16, 8, 4, 0)])
+def test_ragged_tiles(orc, launch):
+    """A grid that fills no tile exactly (70 x 37 x 19), random solids, 20 steps."""
+    shape = (70, 37, 19)
+    nx, ny, nz = shape
+    solid = W.random_geometry(shape, 11, n_blocks=6)
+    phi0 = W.tanh_droplet(shape, (30.2, 17.7, 7.1), 6.0, 4.0).astype(np.float32)
+    w = W.Workload("ragged", shape, solid, W.uniform_theta(shape, 75.0), phi0, W.default_params(), 0)
+    o = oracle_run(orc, w, 20)
+    g = gpu_run(w, 20, launch=launch)
+    _cmp(g, o, w, orc, 5e-6, 5e-5)
+
+
+def test_deterministic_and_graph_replay():
+    """Two identical runs are bitwise equal, and graph replay equals eager launches."""
+    w = W.sessile((40, 36, 20), 7.0, 110.0)
+    a = gpu_run(w, 15, launch=(16, 4, 4, 0))
+    b = gpu_run(w, 15, launch=(16, 4, 4, 0))
+    c = gpu_run(w, 15, launch=(16, 4, 4, 1))
+    for k in ("phi", "u", "f"):
+        np.testing.assert_array_equal(a[k], b[k])
+        np.testing.assert_array_equal(a[k], c[k])
+
+
+def test_uniform_state_invariant_gpu():
+    """Rest state, constant phi, walls: nothing moves (exact in FP32)."""
+    shape = (24, 20, 16)
+    N = 24 * 20 * 16
+    w = W.Workload("rest", shape, W.random_geometry(shape, 2), W.uniform_theta(shape, 40.0),
+                   np.full(N, 0.3, np.float32), W.default_params(), 0)
+    g = gpu_run(w, 10)
+    fl = w.solid == 0
+    assert np.abs(g["phi"][fl] - 0.3).max() < 1e-7
+    assert np.abs(g["u"]).max() < 1e-9
+
+
+def test_volume_conserved_gpu():
+    """Phase-field volume after 300 steps equals the initial one up to FP32
+    storage rounding of phi."""
+    w = W.sessile((48, 48, 24), 9.0, 45.0)
+    g = gpu_run(w, 300)
+    M0 = float(w.phi0.astype(np.float64)[w.solid == 0].sum())
+    assert g["volume"] == pytest.approx(M0, rel=2e-7)
+
+
+def test_full_size_spreading_one_step(orc):
+    """Spreading workload at its full size (256 x 256 x 128), one step: every
+    fluid node of phi, u and p* against the oracle, in the launch configuration
+    the benchmark uses."""
+    from paper_2607_25444_amd import tuning
+    w = W.spreading_256(0)
+    o = oracle_run(orc, w, 1)
+    g = gpu_run(w, 1, launch=tuning.launch_for(w.shape))
+    _cmp(g, o, w, orc, 2e-6, 1e-5, with_f=False)
