@@ -72,6 +72,25 @@ def cpu_baseline(w, steps):
                        f"{dt:.1f} s wall")
 
 
+def copy_probe(torch, nbytes=1 << 30, reps=20):
+    """Elementwise copy of nbytes (read nbytes, write nbytes) with torch's
+    streaming kernel; prints the achieved GB/s as JSON."""
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "ms": round(ms, 4),
+                      "GBs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +101,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default=None, help="bx,by,bz,graph")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="time a plain 1 GiB device copy (HBM ceiling; counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -92,6 +113,10 @@ def main():
     import torch
     from paper_2607_25444_amd import capi, tuning
     from paper_2607_25444_amd import workloads as W
+
+    if args.copy_probe:
+        copy_probe(torch)
+        return
 
     if args.workload == "spreading":
         w = W.spreading_256(args.seed)

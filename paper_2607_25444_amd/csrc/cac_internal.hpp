@@ -77,7 +77,7 @@ struct Fields {
     float *f[2];        // post-collision populations, 27 planes each
     float *phi[2];      // phase field A/B buffers (fluid values + ghosts)
     float *u;           // 3 planes
-    float *a;           // compressive flux phi(1-phi)n, 3 planes (fluid: H, wall: W)
+    float *a;           // compressive flux on wall nodes (3 planes, written by W; zero elsewhere)
     uint32_t *nbr;      // bit 0: node solid; bit i: node + c_i solid
     uint8_t *solid;     // 1 = solid
     int32_t *wall_idx;  // wall-node list (ascending node index)
@@ -98,6 +98,7 @@ hipError_t launch_hydro(const Grid &g, const Tiling &t, const DevParams &p, cons
                         hipStream_t s);
 hipError_t launch_phase(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, int pcur,
                         hipStream_t s);
+uint32_t phase_tiles(const Grid &g);  // workgroups (and FP64 partials) of the phase kernel
 hipError_t launch_volume(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, int pnext,
                          hipStream_t s);
 hipError_t launch_init(const Grid &g, const Fields &F, int fcur, const float *u0, const float *ps0,

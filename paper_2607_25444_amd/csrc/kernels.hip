@@ -242,12 +242,12 @@ __global__ __launch_bounds__(256) void k_ghost(Grid g, DevParams p, const int32_
 //     f*_i = w_i [p* + 3 c.(u + a/2) + 4.5 H2:C2 + 4.5 H3:C3],
 //     C2 = uu + (ua + au)/2 + (1 - omega) A2,  C3 = uuu + (1 - omega) S(u A2),
 //     A2 = P - p*/3 I - uu + (ua + au)/2  (second moment of f - f^eq + S/2).
-//   Writes f*, u and the compressive flux a = phi(1-phi) grad/|grad|.
+//   Writes f* and u.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_hydro(Grid g, Tiling t, DevParams p, const float *__restrict__ fin,
                                               float *__restrict__ fout, const float *__restrict__ phi,
                                               const uint32_t *__restrict__ nbr, float *__restrict__ u,
-                                              float *__restrict__ a, uint32_t *__restrict__ flag)
+                                              uint32_t *__restrict__ flag)
 {
     const Node nd = tile_node(g, t, xcd_tile(blockIdx.x, t.ntiles));
     if (!nd.in) return;
@@ -369,17 +369,6 @@ __global__ __launch_bounds__(NT) void k_hydro(Grid g, Tiling t, DevParams p, con
     u[n] = ux;
     u[N + n] = uy;
     u[2u * N + n] = uz;
-    const float g2 = gx * gx + gy * gy + gz * gz;
-    float cx = 0.f, cy = 0.f, cz = 0.f;
-    if (g2 > p.eps_n2) {
-        const float sc = ph * (1.0f - ph) * rsqrtf(g2);
-        cx = sc * gx;
-        cy = sc * gy;
-        cz = sc * gz;
-    }
-    a[n] = cx;
-    a[N + n] = cy;
-    a[2u * N + n] = cz;
     if (!(isfinite(ux) && isfinite(uy) && isfinite(uz) && isfinite(ps))) flag[0] = 1u;
 }
 
@@ -428,85 +417,353 @@ __device__ __forceinline__ void block_sum2(double &x, double &y)
     }
 }
 
-// CAC update at fluid node x (Eq. (28)):
+// CAC update (Eq. (28)) as a 2.5-D stencil: a workgroup owns a BX x BY
+// column tile and marches up a chunk of ZC planes.  LDS holds a ring of five
+// phi planes (z-2..z+2, halo 2 in x and y) and a ring of three planes of the
+// compressive flux a = phi(1-phi) grad/|grad| (z-1..z+1, halo 1) together
+// with the solid flags.  At each plane: load phi(z+2), build a(z+1) from the
+// isotropic gradient (Eq. (22), normal of Eq. (25)), then update the nodes of
+// plane z:
 //   phi* = phi - div(F_a) + D lap(phi) - kappa div_iso(a)
-// F_a from the MUSCL-minmod face fluxes, zero on faces touching a solid node;
-// div_iso with the weights w_i/c_s^2 (tensor-product form).  Also accumulates
-// sum(phi*) and sum(chi), chi = phi*(1-phi*) inside the band (Eqs. (49), (51)),
-// in FP64 per tile.
-template <int NT>
-__global__ __launch_bounds__(NT) void k_phase(Grid g, Tiling t, DevParams p, const float *__restrict__ phi,
-                                              float *__restrict__ phi_out, const float *__restrict__ u,
-                                              const float *__restrict__ a, const uint32_t *__restrict__ nbr,
-                                              double2 *__restrict__ partial, uint32_t *__restrict__ flag)
+// with MUSCL-minmod face fluxes (Eqs. (29)-(34)), zero on faces touching a
+// solid node, and div_iso with the weights w_i/c_s^2.  On solid nodes a is
+// the value the ghost update assigned (zero unless wall_compression is on).
+// Each thread also accumulates sum(phi*) and sum(chi) (Eqs. (49), (51)) in
+// FP64; the workgroup writes one partial per tile.
+struct PhaseTiling {
+    int ntx, nty, nzc, zc;
+    uint32_t ntiles;
+};
+
+__device__ __forceinline__ int wrapc(int v, int n)
 {
-    const uint32_t tile = xcd_tile(blockIdx.x, t.ntiles);
-    const Node nd = tile_node(g, t, tile);
-    double sphi = 0.0, schi = 0.0;
-    if (nd.in) {
-        const Offs o = node_offsets(g, nd.x, nd.y, nd.z);
-        const uint32_t n = at<0, 0, 0>(o);
-        const uint32_t m = nbr[n];
-        if (!(m & 1u)) {
-            const uint32_t N = g.N;
-            float s[27];
-            static_for<27>([&](auto K) {
-                constexpr int kk = K;
-                s[kk] = phi[at<kk % 3 - 1, (kk / 3) % 3 - 1, kk / 9 - 1>(o)];
-            });
-            float gx, gy, gz, lap;
-            stencil_grad_lap(s, gx, gy, gz, lap);
-            const float ph = s[13];
-            // second neighbours along the axes (wrapped)
-            const int x2m = nd.x >= 2 ? nd.x - 2 : nd.x - 2 + g.nx, x2p = nd.x + 2 < g.nx ? nd.x + 2 : nd.x + 2 - g.nx;
-            const int y2m = nd.y >= 2 ? nd.y - 2 : nd.y - 2 + g.ny, y2p = nd.y + 2 < g.ny ? nd.y + 2 : nd.y + 2 - g.ny;
-            const int z2m = nd.z >= 2 ? nd.z - 2 : nd.z - 2 + g.nz, z2p = nd.z + 2 < g.nz ? nd.z + 2 : nd.z + 2 - g.nz;
-            const uint32_t yz = o.y[1] + o.z[1], xz = o.x[1] + o.z[1], xy = o.x[1] + o.y[1];
-            float div_a = 0.0f;
-            {  // x faces
-                const float umid = u[n];
-                const float pm2 = phi[(uint32_t)x2m + yz], pp2 = phi[(uint32_t)x2p + yz];
-                const float pm = s[12], pp = s[14];
-                if (!((m >> 1) & 1u)) div_a += muscl_flux(pm, ph, pp, pp2, umid, u[o.x[2] + yz]);
-                if (!((m >> 2) & 1u)) div_a -= muscl_flux(pm2, pm, ph, pp, u[o.x[0] + yz], umid);
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// Per-plane partial sums of the tensor-product stencils on a 3x3 plane patch
+// v[3*(dy+1) + (dx+1)] around a column:
+//   sx = sum_dy t(dy) [v(+1,dy) - v(-1,dy)]   (x differences smoothed in y)
+//   sy = sum_dx t(dx) [v(dx,+1) - v(dx,-1)]
+//   tq = sum t(dx) t(dy) [v - v(0,0)]          (smoothed, relative to the centre)
+// A column's gradient and Laplacian over planes -1, 0, +1 follow as
+//   grad_x = (sx_- + 4 sx_0 + sx_+)/72, grad_y likewise with sy,
+//   grad_z = (tq_+ - tq_- + 36 (c_+ - c_-))/72,
+//   lap    = (tq_- + 4 tq_0 + tq_+ + 36 (c_- + c_+ - 2 c_0))/36,
+// the same sums as Eqs. (22)-(23), regrouped plane by plane.
+struct PlaneSums {
+    float sx, sy, tq, c;
+};
+
+__device__ __forceinline__ PlaneSums plane_sums(const float (&v)[9])
+{
+    PlaneSums r;
+    r.c = v[4];
+    r.sx = (v[2] - v[0]) + 4.0f * (v[5] - v[3]) + (v[8] - v[6]);
+    r.sy = (v[6] - v[0]) + 4.0f * (v[7] - v[1]) + (v[8] - v[2]);
+    r.tq = (v[0] - r.c) + (v[2] - r.c) + (v[6] - r.c) + (v[8] - r.c) +
+           4.0f * ((v[1] - r.c) + (v[3] - r.c) + (v[5] - r.c) + (v[7] - r.c));
+    return r;
+}
+
+// minmod of Eq. (32) in branch-free form: equal to 0 when ab <= 0, else the
+// argument of smaller magnitude.
+__device__ __forceinline__ float minmod2(float a, float b)
+{
+    return fmaxf(fminf(a, b), 0.0f) + fminf(fmaxf(a, b), 0.0f);
+}
+
+// The two face fluxes of a node along one axis from phi at offsets -2..+2 and
+// the axial velocity at -1, 0, +1 (Eqs. (30)-(34)); the slope at the node is
+// shared by both faces.  open_m/open_p: the face does not touch a solid node.
+__device__ __forceinline__ float muscl_axis(float q0, float q1, float q2, float q3, float q4, float um, float uc,
+                                            float up, bool open_m, bool open_p)
+{
+    const float d0 = q1 - q0, d1 = q2 - q1, d2 = q3 - q2, d3 = q4 - q3;
+    const float sm = minmod2(d0, d1), sc = minmod2(d1, d2), sp = minmod2(d2, d3);
+    const float ufp = 0.5f * (uc + up), ufm = 0.5f * (um + uc);
+    const float fp = ufp * (ufp >= 0.0f ? q2 + 0.5f * sc : q3 - 0.5f * sp);
+    const float fm = ufm * (ufm >= 0.0f ? q1 + 0.5f * sm : q2 - 0.5f * sc);
+    return (open_p ? fp : 0.0f) - (open_m ? fm : 0.0f);
+}
+
+template <int BX, int BY>
+__global__ __launch_bounds__(BX *BY) void k_phase(Grid g, PhaseTiling pt, DevParams p, const float *__restrict__ phi,
+                                                  float *__restrict__ phi_out, const float *__restrict__ u,
+                                                  const float *__restrict__ aw, const uint8_t *__restrict__ solid,
+                                                  double2 *__restrict__ partial, uint32_t *__restrict__ flag)
+{
+    constexpr int NT = BX * BY;
+    constexpr int HX = BX + 4, HY = BY + 4;  // phi plane, halo 2
+    constexpr int AX = BX + 2, AY = BY + 2;  // flux / flag plane, halo 1
+    constexpr int PF = (HX * HY + NT - 1) / NT;  // phi values per thread per plane
+    constexpr int PA = (AX * AY + NT - 1) / NT;  // flux points per thread per plane
+    __shared__ float sphi[5][HY][HX];
+    __shared__ float sa[3][3][AY][AX];
+    __shared__ uint8_t ssol[3][AY][AX];
+
+    const uint32_t tile = xcd_tile(blockIdx.x, pt.ntiles);
+    const int tcx = (int)(tile % (uint32_t)pt.ntx);
+    const int tcy = (int)((tile / (uint32_t)pt.ntx) % (uint32_t)pt.nty);
+    const int tcz = (int)(tile / ((uint32_t)pt.ntx * (uint32_t)pt.nty));
+    const int x0 = tcx * BX, y0 = tcy * BY, z0 = tcz * pt.zc;
+    const int z1 = min(z0 + pt.zc, g.nz);
+    const int tid = threadIdx.x;
+    const int lx = tid % BX, ly = tid / BX;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool col_in = x < g.nx && y < g.ny;
+    const uint32_t N = g.N;
+
+    auto pslot = [&](int zz) { return (zz - z0 + 10) % 5; };
+    auto aslot = [&](int zz) { return (zz - z0 + 3) % 3; };
+    auto zoff = [&](int zz) { return (uint32_t)wrapc(zz, g.nz) * g.nxny; };
+
+    // this thread's share of the halo planes: global in-plane offset and LDS position
+    uint32_t pxy[PF], axy[PA];
+    int apos[PA];
+#pragma unroll
+    for (int r = 0; r < PF; ++r) {
+        const int k = tid + r * NT;
+        const int hx = k % HX, hy = k / HX;
+        pxy[r] = k < HX * HY ? (uint32_t)wrapc(x0 - 2 + hx, g.nx) + (uint32_t)wrapc(y0 - 2 + hy, g.ny) * (uint32_t)g.nx : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < PA; ++r) {
+        const int k = tid + r * NT;
+        const int ax = k % AX, ay = k / AX;
+        axy[r] = k < AX * AY ? (uint32_t)wrapc(x0 - 1 + ax, g.nx) + (uint32_t)wrapc(y0 - 1 + ay, g.ny) * (uint32_t)g.nx : 0u;
+        apos[r] = k < AX * AY ? ay * AX + ax : -1;
+    }
+    auto fetch_phi = [&](int zz, float (&v)[PF]) {
+        const uint32_t zo = zoff(zz);
+#pragma unroll
+        for (int r = 0; r < PF; ++r)
+            if (tid + r * NT < HX * HY) v[r] = phi[pxy[r] + zo];
+    };
+    auto store_phi = [&](int zz, const float (&v)[PF]) {
+        float *dst = &sphi[pslot(zz)][0][0];
+#pragma unroll
+        for (int r = 0; r < PF; ++r)
+            if (tid + r * NT < HX * HY) dst[tid + r * NT] = v[r];
+    };
+    auto fetch_sol = [&](int zz, uint8_t (&v)[PA]) {
+        const uint32_t zo = zoff(zz);
+#pragma unroll
+        for (int r = 0; r < PA; ++r)
+            if (apos[r] >= 0) v[r] = solid[axy[r] + zo];
+    };
+    auto store_sol = [&](int zz, const uint8_t (&v)[PA]) {
+        uint8_t *dst = &ssol[aslot(zz)][0][0];
+#pragma unroll
+        for (int r = 0; r < PA; ++r)
+            if (apos[r] >= 0) dst[apos[r]] = v[r];
+    };
+    // 3x3 patch of phi plane zz centred on halo-1 position (ax, ay) (= halo-2 position + 1)
+    auto patch = [&](int zz, int ax, int ay, float (&v)[9]) {
+        const float *pl = &sphi[pslot(zz)][0][0];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) v[j] = pl[(ay + j / 3) * HX + ax + j % 3];
+    };
+
+    // rolling plane sums of every flux point this thread builds (planes zz-1, zz)
+    PlaneSums bprev[PA], bcur[PA];
+    auto flux_points_sums = [&](int zz, PlaneSums (&out)[PA]) {
+#pragma unroll
+        for (int r = 0; r < PA; ++r) {
+            if (apos[r] < 0) continue;
+            float v[9];
+            patch(zz, apos[r] % AX, apos[r] / AX, v);
+            out[r] = plane_sums(v);
+        }
+    };
+    // compressive flux plane zz: needs phi planes zz-1..zz+1 (sums of zz-1, zz rolled in)
+    auto build_a = [&](int zz) {
+        const int sl = aslot(zz);
+        const uint32_t zo = zoff(zz);
+        PlaneSums nxt[PA];
+        flux_points_sums(zz + 1, nxt);
+#pragma unroll
+        for (int r = 0; r < PA; ++r) {
+            if (apos[r] < 0) continue;
+            const int pos = apos[r];
+            float cx = 0.f, cy = 0.f, cz = 0.f;
+            if ((&ssol[sl][0][0])[pos]) {
+                if (p.wall_compression) {
+                    const uint32_t id = axy[r] + zo;
+                    cx = aw[id];
+                    cy = aw[N + id];
+                    cz = aw[2u * N + id];
+                }
+            } else {
+                const PlaneSums &m = bprev[r], &c = bcur[r], &q = nxt[r];
+                const float gx = (m.sx + 4.0f * c.sx + q.sx) * (1.0f / 72.0f);
+                const float gy = (m.sy + 4.0f * c.sy + q.sy) * (1.0f / 72.0f);
+                const float gz = (q.tq - m.tq + 36.0f * (q.c - m.c)) * (1.0f / 72.0f);
+                const float g2 = gx * gx + gy * gy + gz * gz;
+                if (g2 > p.eps_n2) {
+                    const float sc = c.c * (1.0f - c.c) * rsqrtf(g2);
+                    cx = sc * gx;
+                    cy = sc * gy;
+                    cz = sc * gz;
+                }
             }
-            {  // y faces
-                const float umid = u[N + n];
-                const float pm2 = phi[(uint32_t)y2m * (uint32_t)g.nx + xz];
-                const float pp2 = phi[(uint32_t)y2p * (uint32_t)g.nx + xz];
-                const float pm = s[10], pp = s[16];
-                if (!((m >> 3) & 1u)) div_a += muscl_flux(pm, ph, pp, pp2, umid, u[N + o.y[2] + xz]);
-                if (!((m >> 4) & 1u)) div_a -= muscl_flux(pm2, pm, ph, pp, u[N + o.y[0] + xz], umid);
-            }
-            {  // z faces
-                const float umid = u[2u * N + n];
-                const float pm2 = phi[(uint32_t)z2m * g.nxny + xy];
-                const float pp2 = phi[(uint32_t)z2p * g.nxny + xy];
-                const float pm = s[4], pp = s[22];
-                if (!((m >> 5) & 1u)) div_a += muscl_flux(pm, ph, pp, pp2, umid, u[2u * N + o.z[2] + xy]);
-                if (!((m >> 6) & 1u)) div_a -= muscl_flux(pm2, pm, ph, pp, u[2u * N + o.z[0] + xy], umid);
-            }
-            // isotropic divergence of the compressive flux (a = 0 on solid nodes
-            // unless the ghost update assigned one)
-            float dx = 0.f, dy = 0.f, dz = 0.f;
-            static_for<9>([&](auto J) {
-                constexpr int j = J;
-                constexpr int e1 = j % 3 - 1, e2 = j / 3 - 1;
-                constexpr float wgt = tw(e1) * tw(e2);
-                dx += wgt * (a[at<1, e1, e2>(o)] - a[at<-1, e1, e2>(o)]);
-                dy += wgt * (a[N + at<e1, 1, e2>(o)] - a[N + at<e1, -1, e2>(o)]);
-                dz += wgt * (a[2u * N + at<e1, e2, 1>(o)] - a[2u * N + at<e1, e2, -1>(o)]);
-            });
-            const float div_c = (dx + dy + dz) * (1.0f / 72.0f);
-            const float ps = ph - div_a + p.D * lap - p.kappa * div_c;
-            phi_out[n] = ps;
-            if (!isfinite(ps)) flag[0] = 1u;
-            sphi = (double)ps;
-            schi = (ps > p.eps_phi && ps < 1.0f - p.eps_phi) ? (double)ps * (1.0 - (double)ps) : 0.0;
+            (&sa[sl][0][0][0])[pos] = cx;
+            (&sa[sl][1][0][0])[pos] = cy;
+            (&sa[sl][2][0][0])[pos] = cz;
+            bprev[r] = bcur[r];
+            bcur[r] = nxt[r];
+        }
+    };
+
+    // velocities this node's fluxes need on plane zz
+    const uint32_t cxy = col_in ? (uint32_t)x + (uint32_t)y * (uint32_t)g.nx : 0u;
+    const uint32_t xm = col_in ? (uint32_t)wrapc(x - 1, g.nx) + (uint32_t)y * (uint32_t)g.nx : 0u;
+    const uint32_t xp = col_in ? (uint32_t)wrapc(x + 1, g.nx) + (uint32_t)y * (uint32_t)g.nx : 0u;
+    const uint32_t ym = col_in ? (uint32_t)x + (uint32_t)wrapc(y - 1, g.ny) * (uint32_t)g.nx : 0u;
+    const uint32_t yp = col_in ? (uint32_t)x + (uint32_t)wrapc(y + 1, g.ny) * (uint32_t)g.nx : 0u;
+    struct UPlane {
+        float xm, xc, xp, ym, yc, yp, zn;  // zn: u_z one plane up
+    };
+    auto fetch_u = [&](int zz, UPlane &v) {
+        if (!col_in) return;
+        const uint32_t zo = zoff(zz);
+        v.xm = u[xm + zo];
+        v.xc = u[cxy + zo];
+        v.xp = u[xp + zo];
+        v.ym = u[N + ym + zo];
+        v.yc = u[N + cxy + zo];
+        v.yp = u[N + yp + zo];
+        v.zn = u[2u * N + cxy + zoff(zz + 1)];
+    };
+
+    const int hx = lx + 2, hy = ly + 2, ax = lx + 1, ay = ly + 1;
+    // column-rolling sums of the output node: Laplacian sums (tq, c) of planes, the
+    // in-plane cross of plane z, and the flux-divergence plane sums
+    auto col_patch = [&](int zz, float (&v)[9]) { patch(zz, lx + 1, ly + 1, v); };
+    auto flux_sums = [&](int zz, float &X, float &Y, float &Z) {
+        const int sl = aslot(zz);
+        const float *fx = &sa[sl][0][0][0], *fy = &sa[sl][1][0][0], *fz = &sa[sl][2][0][0];
+        const int c0 = ay * AX + ax;
+        X = (fx[c0 - AX + 1] - fx[c0 - AX - 1]) + 4.0f * (fx[c0 + 1] - fx[c0 - 1]) + (fx[c0 + AX + 1] - fx[c0 + AX - 1]);
+        Y = (fy[c0 + AX - 1] - fy[c0 - AX - 1]) + 4.0f * (fy[c0 + AX] - fy[c0 - AX]) + (fy[c0 + AX + 1] - fy[c0 - AX + 1]);
+        Z = fz[c0 - AX - 1] + fz[c0 - AX + 1] + fz[c0 + AX - 1] + fz[c0 + AX + 1] +
+            4.0f * (fz[c0 - AX] + fz[c0 - 1] + fz[c0 + 1] + fz[c0 + AX]) + 16.0f * fz[c0];
+    };
+
+    // prologue: phi planes z0-2..z0+1, flags z0-1, z0, flux planes z0-1, z0
+    {
+        float v[PF];
+        uint8_t f8[PA];
+        for (int zz = z0 - 2; zz <= z0 + 1; ++zz) {
+            fetch_phi(zz, v);
+            store_phi(zz, v);
+        }
+        for (int zz = z0 - 1; zz <= z0; ++zz) {
+            fetch_sol(zz, f8);
+            store_sol(zz, f8);
         }
     }
-    block_sum2<NT>(sphi, schi);
-    if (threadIdx.x == 0) partial[tile] = make_double2(sphi, schi);
+    __syncthreads();
+    flux_points_sums(z0 - 2, bprev);
+    flux_points_sums(z0 - 1, bcur);
+    build_a(z0 - 1);
+    build_a(z0);
+    __syncthreads();
+    // output column state for plane z0
+    float tq_m, tq_c, c_m2, c_m, c_c, cr_xm, cr_xp, cr_ym, cr_yp, X_m, X_c, Y_m, Y_c, Z_m, Z_c;
+    {
+        float v[9];
+        col_patch(z0 - 1, v);
+        const PlaneSums sm = plane_sums(v);
+        col_patch(z0, v);
+        const PlaneSums sc = plane_sums(v);
+        tq_m = sm.tq;
+        c_m = sm.c;
+        tq_c = sc.tq;
+        c_c = sc.c;
+        cr_xm = v[3];
+        cr_xp = v[5];
+        cr_ym = v[1];
+        cr_yp = v[7];
+        c_m2 = sphi[pslot(z0 - 2)][hy][hx];
+        flux_sums(z0 - 1, X_m, Y_m, Z_m);
+        flux_sums(z0, X_c, Y_c, Z_c);
+    }
+    float nphi[PF];
+    uint8_t nsol[PA];
+    UPlane uc{}, un{};
+    float uzm = 0.f, uzc = 0.f, uzp = 0.f;
+    fetch_phi(z0 + 2, nphi);
+    fetch_sol(z0 + 1, nsol);
+    fetch_u(z0, uc);
+    if (col_in) {
+        uzm = u[2u * N + cxy + zoff(z0 - 1)];
+        uzc = u[2u * N + cxy + zoff(z0)];
+    }
+    uzp = uc.zn;
+
+    double sphis = 0.0, schi = 0.0;
+    for (int z = z0; z < z1; ++z) {
+        __syncthreads();  // the previous plane is done with the slots overwritten below
+        store_phi(z + 2, nphi);
+        store_sol(z + 1, nsol);
+        if (z + 1 < z1) {  // prefetch for the next plane; lands while this one computes
+            fetch_phi(z + 3, nphi);
+            fetch_sol(z + 2, nsol);
+            fetch_u(z + 1, un);
+        }
+        __syncthreads();
+        build_a(z + 1);
+        __syncthreads();
+        // new column sums of plane z+1 (phi) and flux plane z+1
+        float v[9];
+        col_patch(z + 1, v);
+        const PlaneSums sp = plane_sums(v);
+        float X_p, Y_p, Z_p;
+        flux_sums(z + 1, X_p, Y_p, Z_p);
+        const int sa_c = aslot(z);
+        const uint8_t *fl = &ssol[sa_c][0][0];
+        const int c0 = ay * AX + ax;
+        if (col_in && !fl[c0]) {
+            const float ph = c_c;
+            const float lap = (tq_m + 4.0f * tq_c + sp.tq + 36.0f * ((c_m - ph) + (sp.c - ph))) * (1.0f / 36.0f);
+            const float *p0 = &sphi[pslot(z)][0][0];
+            const int h0 = hy * HX + hx;
+            const float c_p2 = sphi[pslot(z + 2)][hy][hx];
+            float div_a = muscl_axis(p0[h0 - 2], cr_xm, ph, cr_xp, p0[h0 + 2], uc.xm, uc.xc, uc.xp, !fl[c0 - 1], !fl[c0 + 1]);
+            div_a += muscl_axis(p0[h0 - 2 * HX], cr_ym, ph, cr_yp, p0[h0 + 2 * HX], uc.ym, uc.yc, uc.yp, !fl[c0 - AX],
+                                !fl[c0 + AX]);
+            div_a += muscl_axis(c_m2, c_m, ph, sp.c, c_p2, uzm, uzc, uzp, !ssol[aslot(z - 1)][ay][ax], !ssol[aslot(z + 1)][ay][ax]);
+            const float div_c = (X_m + 4.0f * X_c + X_p + Y_m + 4.0f * Y_c + Y_p + Z_p - Z_m) * (1.0f / 72.0f);
+            const float ps = ph - div_a + p.D * lap - p.kappa * div_c;
+            phi_out[cxy + (uint32_t)z * g.nxny] = ps;
+            if (!isfinite(ps)) flag[0] = 1u;
+            sphis += (double)ps;
+            if (ps > p.eps_phi && ps < 1.0f - p.eps_phi) schi += (double)ps * (1.0 - (double)ps);
+        }
+        // roll the column state to plane z+1
+        tq_m = tq_c;
+        tq_c = sp.tq;
+        c_m2 = c_m;
+        c_m = c_c;
+        c_c = sp.c;
+        cr_xm = v[3];
+        cr_xp = v[5];
+        cr_ym = v[1];
+        cr_yp = v[7];
+        X_m = X_c;
+        X_c = X_p;
+        Y_m = Y_c;
+        Y_c = Y_p;
+        Z_m = Z_c;
+        Z_c = Z_p;
+        uc = un;
+        uzm = uzc;
+        uzc = uzp;
+        uzp = un.zn;
+    }
+    block_sum2<NT>(sphis, schi);
+    if (tid == 0) partial[tile] = make_double2(sphis, schi);
 }
 
 // ------------------------------------------------------------------ V: volume
@@ -641,42 +898,60 @@ hipError_t launch_hydro(const Grid &g, const Tiling &t, const DevParams &p, cons
     const int nt = t.bx * t.by * t.bz;
     switch (nt) {
     case 128:
-        k_hydro<128><<<t.ntiles, 128, 0, s>>>(g, t, p, F.f[fcur], F.f[fcur ^ 1], F.phi[pcur], F.nbr, F.u, F.a, F.flag);
+        k_hydro<128><<<t.ntiles, 128, 0, s>>>(g, t, p, F.f[fcur], F.f[fcur ^ 1], F.phi[pcur], F.nbr, F.u, F.flag);
         break;
     case 256:
-        k_hydro<256><<<t.ntiles, 256, 0, s>>>(g, t, p, F.f[fcur], F.f[fcur ^ 1], F.phi[pcur], F.nbr, F.u, F.a, F.flag);
+        k_hydro<256><<<t.ntiles, 256, 0, s>>>(g, t, p, F.f[fcur], F.f[fcur ^ 1], F.phi[pcur], F.nbr, F.u, F.flag);
         break;
     case 512:
-        k_hydro<512><<<t.ntiles, 512, 0, s>>>(g, t, p, F.f[fcur], F.f[fcur ^ 1], F.phi[pcur], F.nbr, F.u, F.a, F.flag);
+        k_hydro<512><<<t.ntiles, 512, 0, s>>>(g, t, p, F.f[fcur], F.f[fcur ^ 1], F.phi[pcur], F.nbr, F.u, F.flag);
         break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+// Column tile of the phase kernel and its z-chunk for a lattice.
+static PhaseTiling phase_tiling(const Grid &g, int bx, int by)
+{
+    PhaseTiling pt{};
+    pt.ntx = (g.nx + bx - 1) / bx;
+    pt.nty = (g.ny + by - 1) / by;
+    int zc = 16;
+    while (zc > 4 && (long)pt.ntx * pt.nty * ((g.nz + zc - 1) / zc) < 1024) zc /= 2;
+    pt.zc = zc;
+    pt.nzc = (g.nz + zc - 1) / zc;
+    pt.ntiles = (uint32_t)pt.ntx * (uint32_t)pt.nty * (uint32_t)pt.nzc;
+    return pt;
+}
+
+uint32_t phase_tiles(const Grid &g)
+{
+    const int bx = g.nx >= 64 ? 64 : (g.nx >= 32 ? 32 : 16);
+    const int by = bx == 64 ? 8 : 16;
+    return phase_tiling(g, bx, by).ntiles;
+}
+
 hipError_t launch_phase(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, int pcur,
                         hipStream_t s)
 {
-    const int nt = t.bx * t.by * t.bz;
-    switch (nt) {
-    case 128:
-        k_phase<128><<<t.ntiles, 128, 0, s>>>(g, t, p, F.phi[pcur], F.phi[pcur ^ 1], F.u, F.a, F.nbr, F.partial, F.flag);
-        break;
-    case 256:
-        k_phase<256><<<t.ntiles, 256, 0, s>>>(g, t, p, F.phi[pcur], F.phi[pcur ^ 1], F.u, F.a, F.nbr, F.partial, F.flag);
-        break;
-    case 512:
-        k_phase<512><<<t.ntiles, 512, 0, s>>>(g, t, p, F.phi[pcur], F.phi[pcur ^ 1], F.u, F.a, F.nbr, F.partial, F.flag);
-        break;
-    default: return hipErrorInvalidValue;
-    }
+    (void)t;
+    const int bx = g.nx >= 64 ? 64 : (g.nx >= 32 ? 32 : 16);
+    const int by = bx == 64 ? 8 : 16;
+    const PhaseTiling pt = phase_tiling(g, bx, by);
+    if (bx == 64)
+        k_phase<64, 8><<<pt.ntiles, 512, 0, s>>>(g, pt, p, F.phi[pcur], F.phi[pcur ^ 1], F.u, F.a, F.solid, F.partial, F.flag);
+    else if (bx == 32)
+        k_phase<32, 16><<<pt.ntiles, 512, 0, s>>>(g, pt, p, F.phi[pcur], F.phi[pcur ^ 1], F.u, F.a, F.solid, F.partial, F.flag);
+    else
+        k_phase<16, 16><<<pt.ntiles, 256, 0, s>>>(g, pt, p, F.phi[pcur], F.phi[pcur ^ 1], F.u, F.a, F.solid, F.partial, F.flag);
     return hipGetLastError();
 }
 
 hipError_t launch_volume(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, int pnext,
                          hipStream_t s)
 {
-    k_vol_finalize<<<1, 1024, 0, s>>>(F.partial, t.ntiles, F.scal, p.volume_correction);
+    k_vol_finalize<<<1, 1024, 0, s>>>(F.partial, phase_tiles(g), F.scal, p.volume_correction);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_vol_apply<<<blocks_for(g.N, 256), 256, 0, s>>>(g.N, F.solid, F.phi[pnext], F.scal, p.eps_phi);

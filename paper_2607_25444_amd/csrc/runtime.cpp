@@ -324,7 +324,7 @@ cac_status cac_init(cac_handle **hp, int nx, int ny, int nz, const cac_params *p
     F.nbr = (uint32_t *)dev_alloc(h, Nf * sizeof(uint32_t));
     F.solid = (uint8_t *)dev_alloc(h, Nf);
     F.pstar0 = (float *)dev_alloc(h, Nf * sizeof(float));
-    h->partial_cap = std::max((size_t)(Nf / 64 + 64), (size_t)h->t.ntiles + 64);
+    h->partial_cap = std::max({(size_t)(Nf / 64 + 64), (size_t)h->t.ntiles + 64, (size_t)phase_tiles(h->g) + 64});
     F.partial = (double2 *)dev_alloc(h, h->partial_cap * sizeof(double2));
     F.scal = (double *)dev_alloc(h, 8 * sizeof(double));
     F.flag = (uint32_t *)dev_alloc(h, 256);

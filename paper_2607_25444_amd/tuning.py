@@ -18,4 +18,6 @@ def launch_for(shape):
     bx = 64 if nx >= 64 else (32 if nx >= 32 else 16)
     by = max(1, min(4, 256 // bx))
     bz = 256 // (bx * by)
+    if nx >= 256:
+        bx, by, bz = 256, 2, 1
     return (bx, by, bz, 1 if n <= (1 << 22) else 0)
