@@ -100,7 +100,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--launch", default=None, help="bx,by,bz,graph")
+    ap.add_argument("--launch", default=None, help="bx,by,bz,graph,phase_tile")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 1 GiB device copy (HBM ceiling; counter calibration)")
     args = ap.parse_args()

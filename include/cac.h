@@ -151,10 +151,12 @@ cac_status cac_get_populations(cac_handle *h, float *d_f);
  * (CAC_ERR_NONFINITE) and any deferred HIP error. */
 cac_status cac_sync(cac_handle *h);
 
-/* Launch shape of the bulk kernels: tile bx * by * bz nodes per workgroup
- * (product 64..1024, bx a multiple of 16).  use_graph: 1 = replay steps from a
- * captured HIP graph.  Errors: CAC_ERR_ARG for an unsupported shape. */
-cac_status cac_set_launch(cac_handle *h, int bx, int by, int bz, int use_graph);
+/* Launch shape.  Hydrodynamic kernel: tile of bx * by * bz nodes per workgroup
+ * (powers of two, bx >= 16, product 128, 256 or 512).  phase_tile: column tile
+ * of the phase-field kernel, 0 = automatic, 1..6 = 64x8, 64x4, 32x8, 32x16,
+ * 16x16, 128x4.  use_graph: 1 = replay steps from captured HIP graphs.
+ * Errors: CAC_ERR_ARG for an unsupported shape. */
+cac_status cac_set_launch(cac_handle *h, int bx, int by, int bz, int phase_tile, int use_graph);
 
 /* Advance nsteps steps like cac_step, with HIP events recorded on the
  * handle's stream around every kernel; adds the elapsed milliseconds of each

@@ -52,7 +52,7 @@ SIGNATURES = {
     "cac_get_fields": (C.c_int, [_hp, _vp, _vp, _vp]),
     "cac_get_populations": (C.c_int, [_hp, _vp]),
     "cac_sync": (C.c_int, [_hp]),
-    "cac_set_launch": (C.c_int, [_hp, C.c_int, C.c_int, C.c_int, C.c_int]),
+    "cac_set_launch": (C.c_int, [_hp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
     "cac_profile_step": (C.c_int, [_hp, C.c_int, C.POINTER(C.c_double)]),
     "cac_destroy": (C.c_int, [_hp]),
     "cac_status_string": (C.c_char_p, [C.c_int]),
@@ -245,8 +245,9 @@ class Sim:
         self._check(self.lib.cac_profile_step(self.h, int(n), ms))
         return list(ms)
 
-    def set_launch(self, bx, by, bz, use_graph=False):
-        self._check(self.lib.cac_set_launch(self.h, int(bx), int(by), int(bz), int(bool(use_graph))))
+    def set_launch(self, bx, by, bz, use_graph=False, phase_tile=0):
+        self._check(self.lib.cac_set_launch(self.h, int(bx), int(by), int(bz), int(phase_tile),
+                                            int(bool(use_graph))))
         return self
 
 

@@ -70,6 +70,7 @@ struct Tiling {
     int bx, by, bz;
     int tx, ty, tz;   // tiles per axis
     uint32_t ntiles;  // tx*ty*tz
+    int phase;        // column tile code of the phase kernel (0 = automatic)
 };
 
 // Device buffers of one lattice (plain handle or one batched domain).
@@ -98,7 +99,8 @@ hipError_t launch_hydro(const Grid &g, const Tiling &t, const DevParams &p, cons
                         hipStream_t s);
 hipError_t launch_phase(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, int pcur,
                         hipStream_t s);
-uint32_t phase_tiles(const Grid &g);  // workgroups (and FP64 partials) of the phase kernel
+uint32_t phase_tiles(const Grid &g, const Tiling &t);  // workgroups (and FP64 partials) of the phase kernel
+uint32_t phase_tiles_max(const Grid &g);                // over every phase tile shape
 hipError_t launch_volume(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, int pnext,
                          hipStream_t s);
 hipError_t launch_init(const Grid &g, const Fields &F, int fcur, const float *u0, const float *ps0,

@@ -14,6 +14,8 @@
 //
 // Every kernel bounds-checks its node against the grid; bulk kernels map
 // workgroups to tiles so that each XCD works on a contiguous range of tiles.
+#include <algorithm>
+
 #include "cac_internal.hpp"
 
 namespace cac {
@@ -925,33 +927,64 @@ static PhaseTiling phase_tiling(const Grid &g, int bx, int by)
     return pt;
 }
 
-uint32_t phase_tiles(const Grid &g)
+// Column tile of the phase kernel: code 0 = automatic, else one of the instantiated shapes.
+static void phase_shape(const Grid &g, int code, int &bx, int &by)
 {
-    const int bx = g.nx >= 64 ? 64 : (g.nx >= 32 ? 32 : 16);
-    const int by = bx == 64 ? 8 : 16;
+    switch (code) {
+    case 1: bx = 64; by = 8; return;
+    case 2: bx = 64; by = 4; return;
+    case 3: bx = 32; by = 8; return;
+    case 4: bx = 32; by = 16; return;
+    case 5: bx = 16; by = 16; return;
+    case 6: bx = 128; by = 4; return;
+    default: break;
+    }
+    bx = g.nx >= 64 ? 64 : (g.nx >= 32 ? 32 : 16);
+    by = bx == 64 ? 8 : 16;
+}
+
+uint32_t phase_tiles(const Grid &g, const Tiling &t)
+{
+    int bx, by;
+    phase_shape(g, t.phase, bx, by);
     return phase_tiling(g, bx, by).ntiles;
+}
+
+uint32_t phase_tiles_max(const Grid &g)
+{
+    // the largest tile count over all shapes (sizes the partial-sum buffer)
+    uint32_t m = 0;
+    const int shapes[6][2] = {{64, 8}, {64, 4}, {32, 8}, {32, 16}, {16, 16}, {128, 4}};
+    for (auto &sh : shapes) m = std::max(m, phase_tiling(g, sh[0], sh[1]).ntiles);
+    return m;
 }
 
 hipError_t launch_phase(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, int pcur,
                         hipStream_t s)
 {
-    (void)t;
-    const int bx = g.nx >= 64 ? 64 : (g.nx >= 32 ? 32 : 16);
-    const int by = bx == 64 ? 8 : 16;
+    int bx, by;
+    phase_shape(g, t.phase, bx, by);
     const PhaseTiling pt = phase_tiling(g, bx, by);
-    if (bx == 64)
-        k_phase<64, 8><<<pt.ntiles, 512, 0, s>>>(g, pt, p, F.phi[pcur], F.phi[pcur ^ 1], F.u, F.a, F.solid, F.partial, F.flag);
-    else if (bx == 32)
-        k_phase<32, 16><<<pt.ntiles, 512, 0, s>>>(g, pt, p, F.phi[pcur], F.phi[pcur ^ 1], F.u, F.a, F.solid, F.partial, F.flag);
-    else
-        k_phase<16, 16><<<pt.ntiles, 256, 0, s>>>(g, pt, p, F.phi[pcur], F.phi[pcur ^ 1], F.u, F.a, F.solid, F.partial, F.flag);
-    return hipGetLastError();
+#define CAC_PHASE(BX_, BY_)                                                                                           \
+    if (bx == BX_ && by == BY_) {                                                                                     \
+        k_phase<BX_, BY_><<<pt.ntiles, BX_ * BY_, 0, s>>>(g, pt, p, F.phi[pcur], F.phi[pcur ^ 1], F.u, F.a, F.solid, \
+                                                          F.partial, F.flag);                                         \
+        return hipGetLastError();                                                                                     \
+    }
+    CAC_PHASE(64, 8)
+    CAC_PHASE(64, 4)
+    CAC_PHASE(32, 8)
+    CAC_PHASE(32, 16)
+    CAC_PHASE(16, 16)
+    CAC_PHASE(128, 4)
+#undef CAC_PHASE
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_volume(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, int pnext,
                          hipStream_t s)
 {
-    k_vol_finalize<<<1, 1024, 0, s>>>(F.partial, phase_tiles(g), F.scal, p.volume_correction);
+    k_vol_finalize<<<1, 1024, 0, s>>>(F.partial, phase_tiles(g, t), F.scal, p.volume_correction);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_vol_apply<<<blocks_for(g.N, 256), 256, 0, s>>>(g.N, F.solid, F.phi[pnext], F.scal, p.eps_phi);

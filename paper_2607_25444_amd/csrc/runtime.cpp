@@ -324,7 +324,7 @@ cac_status cac_init(cac_handle **hp, int nx, int ny, int nz, const cac_params *p
     F.nbr = (uint32_t *)dev_alloc(h, Nf * sizeof(uint32_t));
     F.solid = (uint8_t *)dev_alloc(h, Nf);
     F.pstar0 = (float *)dev_alloc(h, Nf * sizeof(float));
-    h->partial_cap = std::max({(size_t)(Nf / 64 + 64), (size_t)h->t.ntiles + 64, (size_t)phase_tiles(h->g) + 64});
+    h->partial_cap = std::max({(size_t)(Nf / 64 + 64), (size_t)h->t.ntiles + 64, (size_t)phase_tiles_max(h->g) + 64});
     F.partial = (double2 *)dev_alloc(h, h->partial_cap * sizeof(double2));
     F.scal = (double *)dev_alloc(h, 8 * sizeof(double));
     F.flag = (uint32_t *)dev_alloc(h, 256);
@@ -538,13 +538,15 @@ cac_status cac_get_populations(cac_handle *h, float *d_f)
     return CAC_OK;
 }
 
-cac_status cac_set_launch(cac_handle *h, int bx, int by, int bz, int use_graph)
+cac_status cac_set_launch(cac_handle *h, int bx, int by, int bz, int phase_tile, int use_graph)
 {
     if (!h) return CAC_ERR_ARG;
     const int nt = bx * by * bz;
     if (!pow2(bx) || !pow2(by) || !pow2(bz) || bx < 16 || (nt != 128 && nt != 256 && nt != 512))
         return fail(h, CAC_ERR_ARG, "unsupported tile %dx%dx%d", bx, by, bz);
+    if (phase_tile < 0 || phase_tile > 6) return fail(h, CAC_ERR_ARG, "unsupported phase tile %d", phase_tile);
     Tiling t = make_tiling(h->g, bx, by, bz);
+    t.phase = phase_tile;
     if (t.ntiles > h->partial_cap) return fail(h, CAC_ERR_ARG, "too many tiles");
     h->t = t;
     h->use_graph = use_graph != 0;

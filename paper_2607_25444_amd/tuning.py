@@ -11,8 +11,11 @@ CANDIDATES = [
 ]
 
 
+PHASE_TILES = {1: (64, 8), 2: (64, 4), 3: (32, 8), 4: (32, 16), 5: (16, 16), 6: (128, 4)}
+
+
 def launch_for(shape):
-    """(bx, by, bz, use_graph) for a lattice of this shape."""
+    """(bx, by, bz, use_graph, phase_tile) for a lattice of this shape."""
     nx, ny, nz = shape
     n = nx * ny * nz
     bx = 64 if nx >= 64 else (32 if nx >= 32 else 16)
@@ -20,4 +23,4 @@ def launch_for(shape):
     bz = 256 // (bx * by)
     if nx >= 256:
         bx, by, bz = 256, 2, 1
-    return (bx, by, bz, 1 if n <= (1 << 22) else 0)
+    return (bx, by, bz, 1 if n <= (1 << 22) else 0, 0)

@@ -120,7 +120,8 @@ def test_sessile_200_steps(orc, wc):
     assert g["volume"] == pytest.approx(o["M"], rel=1e-6)
 
 
-@pytest.mark.parametrize("launch", [None, (16, 4, 4, 0), (32, 2, 4, 1), (16, 8, 4, 0)])
+@pytest.mark.parametrize("launch", [None, (16, 4, 4, 0, 5), (32, 2, 4, 1, 3), (16, 8, 4, 0, 2), (64, 2, 2, 0, 1),
+                                    (128, 2, 1, 0, 6), (32, 4, 4, 0, 4)])
 def test_ragged_tiles(orc, launch):
     """A grid that fills no tile exactly (70 x 37 x 19), random solids, 20 steps."""
     shape = (70, 37, 19)
