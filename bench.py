@@ -91,6 +91,62 @@ def copy_probe(torch, nbytes=1 << 30, reps=20):
                       "GBs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}), flush=True)
 
 
+def bench_batch(torch, capi, W, steps, warmup, seed, singles=True, tune_cache=None):
+    from paper_2607_25444_amd import tuning
+
+    """Batched persistent step over 64 droplet domains (edges from {32,48,64,96,128},
+    R = L/4, angle in [30, 150]); autotuned schedule, graph replay."""
+    ws = W.batch_domains(seed)
+    t0 = time.perf_counter()
+    b = capi.Batch(ws)
+    t_init = time.perf_counter() - t0
+    ndom, ntot, nfl = b.info()
+    tune_ms = b.autotune(tune_cache, trial_steps=3)
+    sched = b.schedule()
+    b.step(warmup)
+    b.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(b.stream)
+    b.step(steps)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    b.sync()
+    kms = [v / 20 for v in b.profile_step(20)]
+    vols = b.volumes()
+    b.close()
+    del b
+    out = {"workload": f"{ndom} domains, edges {sorted(set(w.shape[0] for w in ws))}", "domains": ndom,
+           "nodes": ntot, "fluid_nodes": nfl, "steps": steps, "ms_per_step": round(ms, 5),
+           "value": round(nfl / (ms * 1e-3) / 1e6, 2), "unit": "MLUPS",
+           "algorithmic_frac_of_peak": round(nfl * STEP_BYTES_PER_LU / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "schedule": {"hydro_tile": list(sched[:3]), "phase_tile": sched[3], "grid_mult": sched[4],
+                        "order": sched[5], "graph": sched[6]},
+           "autotune_best_ms": round(tune_ms, 5), "init_s": round(t_init, 2),
+           "kernel_ms": {"W": round(kms[0], 5), "H": round(kms[1], 5), "P": round(kms[2], 5), "V": round(kms[3], 5)}}
+    if singles:
+        # the same domains advanced one after another, each by its own single-lattice handle
+        tot = 0.0
+        for w in ws:
+            sim = capi.Sim(w.shape, w.params)
+            sim.set_launch(*tuning.launch_for(w.shape))
+            sim.set_geometry(w.solid, w.theta)
+            sim.set_state(w.phi0)
+            sim.step(3)
+            sim.sync()
+            a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a0.record(sim.stream)
+            sim.step(20)
+            a1.record(sim.stream)
+            torch.cuda.synchronize()
+            tot += a0.elapsed_time(a1) / 20
+            sim.close()
+        out["singles_ms_per_step"] = round(tot, 5)
+        out["speedup_vs_singles"] = round(tot / ms, 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +157,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default=None, help="bx,by,bz,graph,phase_tile")
+    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 1 GiB device copy (HBM ceiling; counter calibration)")
     args = ap.parse_args()
@@ -111,7 +169,8 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2607_25444_amd import capi, tuning
+    from paper_2607_25444_amd import capi
+    from paper_2607_25444_amd import tuning
     from paper_2607_25444_amd import workloads as W
 
     if args.copy_probe:
@@ -207,6 +266,12 @@ def main():
         },
     }
     sim.close()
+    del sim
+    if not args.no_batch:
+        log("[bench] batched workload ...")
+        rec["batched"] = bench_batch(torch, capi, W, args.batch_steps, 10, args.seed)
+        rec["batched"]["ratio_to_plain"] = round(rec["batched"]["value"] / rec["value"], 4)
+        log(f"[bench] batched {rec['batched']}")
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host ...")
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)

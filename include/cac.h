@@ -167,6 +167,70 @@ cac_status cac_profile_step(cac_handle *h, int nsteps, double *ms);
 /* Release the handle and the device memory it allocated itself. */
 cac_status cac_destroy(cac_handle *h);
 
+/* ------------------------------------------------------------------------
+ * Batched step: many independent lattices ("domains") of uneven size, contact
+ * angle and parameters advanced together, one launch per substep, by
+ * persistent workgroups that walk a list of (domain, tile) work items.  The
+ * step of every domain is the single-lattice step above (Sec. II); the batch
+ * is an execution arrangement, not a change of the method.  Domain k's fields
+ * keep the single-lattice layout in its own slice of shared device arrays.
+ * ------------------------------------------------------------------------ */
+typedef struct cac_batch cac_batch;
+
+typedef struct {
+    int nx, ny, nz;          /* each >= 2 */
+    cac_params params;
+    const uint8_t *solid;    /* host, N bytes, 1 = solid */
+    const float *theta_rad;  /* host, N floats read at wall nodes, or NULL (pi/2) */
+    const float *d_phi0;     /* device, N floats: initial phi (values on wall nodes = initial ghosts) */
+} cac_domain_desc;
+
+/* Create a batch of ndom (1..65535) domains on the current device, geometry
+ * and initial state included (populations at rest equilibrium, M_target per
+ * domain in FP64).  The total 27 * sum(N) must fit in 31 bits.  Errors:
+ * CAC_ERR_ARG (sizes, parameters, null pointers), CAC_ERR_ALLOC, CAC_ERR_HIP. */
+cac_status cac_batch_init(cac_batch **b, int ndom, const cac_domain_desc *d, cac_alloc_fn alloc, void *alloc_user,
+                          void *hip_stream);
+
+/* Block schedule: hydrodynamic tile bx * by * bz (as in cac_set_launch; bx = 0
+ * fits a tile of `by` nodes to every domain, its x extent the largest power of
+ * two dividing nx), phase
+ * column tile code 1..6, persistent grid = grid_mult x resident workgroups per
+ * CU x CUs (0: one workgroup per item), order 0 = domains in input order,
+ * 1 = largest first; use_graph replays steps from captured HIP graphs. */
+cac_status cac_batch_set_schedule(cac_batch *b, int bx, int by, int bz, int phase_tile, int grid_mult, int order,
+                                  int use_graph);
+/* Current schedule as 7 ints in the order of cac_batch_set_schedule. */
+cac_status cac_batch_get_schedule(cac_batch *b, int *out7);
+
+/* Choose the schedule by timing trial_steps steps per candidate (coordinate
+ * search over the tile, the phase tile, the grid multiplier and the order).
+ * The state is saved before and restored after.  cache_path (or NULL): JSON
+ * file of schedules keyed by device and the histogram of domain shapes; a
+ * matching entry is applied without timing (*best_ms = -1).  Synchronises. */
+cac_status cac_batch_autotune(cac_batch *b, const char *cache_path, int trial_steps, double *best_ms);
+
+/* Advance every domain nsteps steps.  Asynchronous. */
+cac_status cac_batch_step(cac_batch *b, int nsteps);
+
+/* Wait; CAC_ERR_NONFINITE if any domain produced a non-finite value. */
+cac_status cac_batch_sync(cac_batch *b);
+
+/* Phase-field volume of every domain (host out[ndom], FP64).  Synchronises. */
+cac_status cac_batch_volume(cac_batch *b, double *out);
+
+/* Fields of domain k, as cac_get_fields (device outputs, any may be NULL). */
+cac_status cac_batch_get_fields(cac_batch *b, int k, float *d_phi, float *d_u, float *d_pstar);
+
+/* Number of domains and total / fluid node counts (any output may be NULL). */
+cac_status cac_batch_info(cac_batch *b, int *ndom, long long *total_nodes, long long *fluid_nodes);
+
+/* As cac_profile_step for the batch: adds per-substep milliseconds (W, H, P, V). */
+cac_status cac_batch_profile(cac_batch *b, int nsteps, double *ms);
+
+cac_status cac_batch_destroy(cac_batch *b);
+cac_status cac_batch_last_error(cac_batch *b, char *buf, size_t n);
+
 const char *cac_status_string(cac_status s);
 
 /* Copy the message of the last failed call on h into buf (n bytes). */

@@ -35,6 +35,11 @@ class CacParams(C.Structure):
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 
+
+class DomainDesc(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("params", CacParams),
+                ("solid", C.c_void_p), ("theta_rad", C.c_void_p), ("d_phi0", C.c_void_p)]
+
 # symbol -> (restype, argtypes); every symbol declared in include/cac.h
 _vp = C.c_void_p
 _hp = C.c_void_p
@@ -55,6 +60,18 @@ SIGNATURES = {
     "cac_set_launch": (C.c_int, [_hp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
     "cac_profile_step": (C.c_int, [_hp, C.c_int, C.POINTER(C.c_double)]),
     "cac_destroy": (C.c_int, [_hp]),
+    "cac_batch_init": (C.c_int, [C.POINTER(_hp), C.c_int, C.POINTER(DomainDesc), ALLOC_FN, _vp, _vp]),
+    "cac_batch_set_schedule": (C.c_int, [_hp] + [C.c_int] * 7),
+    "cac_batch_get_schedule": (C.c_int, [_hp, C.POINTER(C.c_int)]),
+    "cac_batch_autotune": (C.c_int, [_hp, C.c_char_p, C.c_int, C.POINTER(C.c_double)]),
+    "cac_batch_step": (C.c_int, [_hp, C.c_int]),
+    "cac_batch_sync": (C.c_int, [_hp]),
+    "cac_batch_volume": (C.c_int, [_hp, C.POINTER(C.c_double)]),
+    "cac_batch_get_fields": (C.c_int, [_hp, C.c_int, _vp, _vp, _vp]),
+    "cac_batch_info": (C.c_int, [_hp, C.POINTER(C.c_int), C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]),
+    "cac_batch_profile": (C.c_int, [_hp, C.c_int, C.POINTER(C.c_double)]),
+    "cac_batch_destroy": (C.c_int, [_hp]),
+    "cac_batch_last_error": (C.c_int, [_hp, C.c_char_p, C.c_size_t]),
     "cac_status_string": (C.c_char_p, [C.c_int]),
     "cac_last_error": (C.c_int, [_hp, C.c_char_p, C.c_size_t]),
 }
@@ -261,3 +278,115 @@ def from_workload(w, device=None) -> Sim:
 
 def pi_half() -> float:
     return math.pi / 2
+
+
+class Batch:
+    """Many independent domains advanced together by the persistent batched kernels."""
+
+    def __init__(self, workloads, device=None, stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("libcac needs a GPU (torch.cuda.is_available() is False)")
+        self.torch = torch
+        self.lib = load_library()
+        self.device = torch.device(device or "cuda")
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        self._buffers = []
+
+        def _alloc(nbytes, user):
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+            self._buffers.append(t)
+            return t.data_ptr()
+
+        self._alloc_cb = ALLOC_FN(_alloc)
+        self.shapes = [tuple(w.shape) for w in workloads]
+        n = len(workloads)
+        descs = (DomainDesc * n)()
+        keep = []
+        for k, w in enumerate(workloads):
+            solid = np.ascontiguousarray(w.solid, dtype=np.uint8).reshape(-1)
+            th = np.ascontiguousarray(w.theta, dtype=np.float32).reshape(-1)
+            phi = torch.as_tensor(w.phi0, dtype=torch.float32, device=self.device).contiguous().reshape(-1)
+            keep += [solid, th, phi]
+            descs[k].nx, descs[k].ny, descs[k].nz = w.shape
+            descs[k].params = make_params(w.params)
+            descs[k].solid = solid.ctypes.data_as(C.c_void_p)
+            descs[k].theta_rad = th.ctypes.data_as(C.c_void_p)
+            descs[k].d_phi0 = C.c_void_p(phi.data_ptr())
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            st = self.lib.cac_batch_init(C.byref(h), n, descs, self._alloc_cb, None, C.c_void_p(self.stream.cuda_stream))
+        if st != CAC_OK:
+            raise CacError(st, "cac_batch_init: " + self.lib.cac_status_string(st).decode())
+        self.h = h
+        self.ndom = n
+        self.sync()
+        del keep
+
+    def _check(self, st):
+        if st == CAC_OK:
+            return
+        buf = C.create_string_buffer(512)
+        self.lib.cac_batch_last_error(self.h, buf, 512)
+        raise CacError(st, self.lib.cac_status_string(st).decode() + ": " + buf.value.decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.cac_batch_destroy(self.h)
+            self.h = None
+            self._buffers.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_schedule(self, bx, by, bz, phase_tile, grid_mult, order, use_graph=True):
+        self._check(self.lib.cac_batch_set_schedule(self.h, bx, by, bz, phase_tile, grid_mult, order, int(use_graph)))
+        return self
+
+    def schedule(self):
+        out = (C.c_int * 7)()
+        self._check(self.lib.cac_batch_get_schedule(self.h, out))
+        return tuple(out)
+
+    def autotune(self, cache_path=None, trial_steps=5):
+        ms = C.c_double()
+        self._check(self.lib.cac_batch_autotune(self.h, None if cache_path is None else cache_path.encode(),
+                                                int(trial_steps), C.byref(ms)))
+        return ms.value
+
+    def step(self, n=1):
+        self._check(self.lib.cac_batch_step(self.h, int(n)))
+        return self
+
+    def sync(self):
+        self._check(self.lib.cac_batch_sync(self.h))
+        return self
+
+    def volumes(self):
+        out = (C.c_double * self.ndom)()
+        self._check(self.lib.cac_batch_volume(self.h, out))
+        return list(out)
+
+    def fields(self, k):
+        tc = self.torch
+        nx, ny, nz = self.shapes[k]
+        N = nx * ny * nz
+        phi = tc.empty(N, dtype=tc.float32, device=self.device)
+        u = tc.empty(3 * N, dtype=tc.float32, device=self.device)
+        ps = tc.empty(N, dtype=tc.float32, device=self.device)
+        self._check(self.lib.cac_batch_get_fields(self.h, int(k), _ptr(phi), _ptr(u), _ptr(ps)))
+        return phi, u, ps
+
+    def info(self):
+        n, tot, fl = C.c_int(), C.c_longlong(), C.c_longlong()
+        self._check(self.lib.cac_batch_info(self.h, C.byref(n), C.byref(tot), C.byref(fl)))
+        return n.value, tot.value, fl.value
+
+    def profile_step(self, n):
+        ms = (C.c_double * 4)()
+        self._check(self.lib.cac_batch_profile(self.h, int(n), ms))
+        return list(ms)

@@ -1,0 +1,259 @@
+// batch.hip -- persistent batched kernels: many independent lattices of
+// uneven size and contact angle advanced by one launch per substep.
+//
+// A fixed grid of workgroups (sized from the occupancy of the kernel) walks a
+// host-built list of (domain, tile) work items with stride gridDim.x; each
+// item runs the same device body as the single-lattice kernels on that
+// domain's slice of the concatenated arrays.  Volume sums are kept per domain
+// (partial index = the domain's first partial + its tile), so the FP64 totals
+// do not depend on the schedule.
+#include "step_device.hpp"
+
+namespace cac {
+
+// Pointers of one domain for buffer parity `cur`, chosen with selects (a
+// runtime-indexed local array would be placed in scratch memory).
+struct DomPtrs {
+    const float *fin;
+    float *fout;
+    float *phi_cur, *phi_oth;
+    float *u, *a;
+    const uint32_t *nbr;
+    const uint8_t *solid;
+};
+
+__device__ __forceinline__ DomPtrs domain_ptrs(const BatchPtrs &B, const BatchDomain &d, int cur)
+{
+    DomPtrs P;
+    float *f0 = B.f[0], *f1 = B.f[1], *p0 = B.phi[0], *p1 = B.phi[1];
+    P.fin = (cur ? f1 : f0) + 27u * d.off;
+    P.fout = (cur ? f0 : f1) + 27u * d.off;
+    P.phi_cur = (cur ? p1 : p0) + d.off;
+    P.phi_oth = (cur ? p0 : p1) + d.off;
+    P.u = B.u + 3u * d.off;
+    P.a = B.a + 3u * d.off;
+    P.nbr = B.nbr + d.off;
+    P.solid = B.solid + d.off;
+    return P;
+}
+
+// Items of this workgroup.  One workgroup per item: the XCD-aware renumbering
+// of the single-lattice kernels.  Persistent grid (a multiple of 8): XCD x =
+// blockIdx % 8 owns the contiguous eighth x of the item list and its
+// workgroups stride through it, so neighbouring tiles share that XCD's L2.
+struct ItemRange {
+    uint32_t first, end, stride;
+};
+
+__device__ __forceinline__ ItemRange item_range(uint32_t nitems)
+{
+    const uint32_t G = gridDim.x, b = blockIdx.x;
+    ItemRange r;
+    if (G >= nitems) {
+        r.first = b < nitems ? xcd_tile(b, nitems) : nitems;
+        r.end = r.first < nitems ? r.first + 1 : nitems;
+        r.stride = 1;
+    } else if ((G & 7u) == 0) {
+        const uint32_t x = b & 7u;
+        r.first = (uint32_t)(((uint64_t)nitems * x) >> 3) + (b >> 3);
+        r.end = (uint32_t)(((uint64_t)nitems * (x + 1)) >> 3);
+        r.stride = G >> 3;
+    } else {
+        r.first = b;
+        r.end = nitems;
+        r.stride = G;
+    }
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_bghost(BatchPtrs B, const BatchDomain *__restrict__ dom, uint32_t nwall,
+                                                int cur)
+{
+    const uint32_t k = blockIdx.x * 256u + threadIdx.x;
+    if (k >= nwall) return;
+    const BatchDomain d = dom[B.wall_dom[k]];
+    const DomPtrs P = domain_ptrs(B, d, cur);
+    ghost_node(d.g, d.p, (int)k, B.wall_idx, B.wall_q, B.wall_n, B.theta, P.phi_cur, P.phi_oth, P.nbr, P.a);
+}
+
+// The descriptor array is a separate read-only, non-aliased argument so that
+// its uniform fields are fetched with scalar loads into scalar registers.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_bhydro(BatchPtrs B, const BatchDomain *__restrict__ dom,
+                                               const uint2 *__restrict__ items, uint32_t nitems, int cur)
+{
+    const ItemRange r = item_range(nitems);
+    uint2 nxt = r.first < r.end ? items[r.first] : make_uint2(0u, 0u);
+    for (uint32_t it = r.first; it < r.end; it += r.stride) {
+        const uint2 dt = nxt;
+        if (it + r.stride < r.end) nxt = items[it + r.stride];  // next record loads during this item
+        const BatchDomain d = dom[dt.x];
+        const DomPtrs P = domain_ptrs(B, d, cur);
+        hydro_node(d.g, d.p, tile_node(d.g, d.t, dt.y), P.fin, P.fout, P.phi_cur, P.nbr, P.u, B.flag);
+    }
+}
+
+// One workgroup per item (the schedule's grid multiplier 0): no loop state.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_bhydro1(BatchPtrs B, const BatchDomain *__restrict__ dom,
+                                                const uint2 *__restrict__ items, uint32_t nitems, int cur)
+{
+    const uint2 dt = items[xcd_tile(blockIdx.x, nitems)];
+    const BatchDomain d = dom[dt.x];
+    const DomPtrs P = domain_ptrs(B, d, cur);
+    hydro_node(d.g, d.p, tile_node(d.g, d.t, dt.y), P.fin, P.fout, P.phi_cur, P.nbr, P.u, B.flag);
+}
+
+template <int BX, int BY>
+__global__ __launch_bounds__(BX *BY) void k_bphase(BatchPtrs B, const BatchDomain *__restrict__ dom,
+                                                   const uint2 *__restrict__ items, uint32_t nitems, int cur)
+{
+    const ItemRange r = item_range(nitems);
+    uint2 nxt = r.first < r.end ? items[r.first] : make_uint2(0u, 0u);
+    for (uint32_t it = r.first; it < r.end; it += r.stride) {
+        __syncthreads();  // the previous item is done with the workgroup's LDS
+        const uint2 dt = nxt;
+        if (it + r.stride < r.end) nxt = items[it + r.stride];
+        const BatchDomain d = dom[dt.x];
+        const DomPtrs P = domain_ptrs(B, d, cur);
+        phase_tile<BX, BY>(d.g, d.pt, d.p, dt.y, P.phi_cur, P.phi_oth, P.u, P.a, P.solid,
+                           B.partial + d.p_item0 + dt.y, B.flag);
+    }
+}
+
+// One workgroup per domain: lambda_k from its tile partials in a fixed order.
+__global__ __launch_bounds__(256) void k_bvol_finalize(BatchPtrs B, const BatchDomain *__restrict__ dom)
+{
+    const BatchDomain d = dom[blockIdx.x];
+    double x = 0.0, y = 0.0;
+    for (uint32_t k = threadIdx.x; k < d.pt.ntiles; k += 256u) {
+        const double2 v = B.partial[d.p_item0 + k];
+        x += v.x;
+        y += v.y;
+    }
+    block_sum2<256>(x, y);
+    if (threadIdx.x == 0) {
+        double *sc = B.scal + 8u * blockIdx.x;
+        const double lam = (d.p.volume_correction && y > 0.0) ? (sc[0] - x) / y : 0.0;
+        sc[1] = lam;
+        sc[2] = x;
+        sc[3] = y;
+    }
+}
+
+// phi <- phi* + lambda_k chi(phi*) on the fluid nodes of the hydro tiles.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_bvol_apply(BatchPtrs B, const BatchDomain *__restrict__ dom,
+                                                   const uint2 *__restrict__ items, uint32_t nitems, int cur_next)
+{
+    const ItemRange r = item_range(nitems);
+    for (uint32_t it = r.first; it < r.end; it += r.stride) {
+        const uint2 dt = items[it];
+        const BatchDomain d = dom[dt.x];
+        const Node nd = tile_node(d.g, d.t, dt.y);
+        if (!nd.in) continue;
+        const uint32_t n = (uint32_t)nd.x + (uint32_t)d.g.nx * ((uint32_t)nd.y + (uint32_t)d.g.ny * (uint32_t)nd.z);
+        if (B.solid[d.off + n]) continue;
+        float *phi = (cur_next ? B.phi[1] : B.phi[0]) + d.off;
+        const float v = phi[n];
+        const float eps = d.p.eps_phi;
+        if (v > eps && v < 1.0f - eps) {
+            const double lam = B.scal[8u * dt.x + 1];
+            phi[n] = (float)((double)v + lam * ((double)v * (1.0 - (double)v)));
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t launch_bghost(const BatchPtrs &B, uint32_t nwall, int cur, hipStream_t s)
+{
+    if (!nwall) return hipSuccess;
+    k_bghost<<<(nwall + 255u) / 256u, 256, 0, s>>>(B, B.dom, nwall, cur);
+    return hipGetLastError();
+}
+
+hipError_t launch_bhydro(const BatchPtrs &B, int nt, const uint2 *items, uint32_t nitems, uint32_t grid, int cur,
+                         hipStream_t s)
+{
+    if (!nitems) return hipSuccess;
+    switch (nt) {
+    case 128:
+        if (grid >= nitems) k_bhydro1<128><<<nitems, 128, 0, s>>>(B, B.dom, items, nitems, cur);
+        else k_bhydro<128><<<grid, 128, 0, s>>>(B, B.dom, items, nitems, cur);
+        break;
+    case 256:
+        if (grid >= nitems) k_bhydro1<256><<<nitems, 256, 0, s>>>(B, B.dom, items, nitems, cur);
+        else k_bhydro<256><<<grid, 256, 0, s>>>(B, B.dom, items, nitems, cur);
+        break;
+    case 512:
+        if (grid >= nitems) k_bhydro1<512><<<nitems, 512, 0, s>>>(B, B.dom, items, nitems, cur);
+        else k_bhydro<512><<<grid, 512, 0, s>>>(B, B.dom, items, nitems, cur);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bphase(const BatchPtrs &B, int code, const uint2 *items, uint32_t nitems, uint32_t grid, int cur,
+                         hipStream_t s)
+{
+    if (!nitems) return hipSuccess;
+    int bx, by;
+    phase_shape_of(code, bx, by);
+#define CAC_BPHASE(BX_, BY_)                                                        \
+    if (bx == BX_ && by == BY_) {                                                   \
+        k_bphase<BX_, BY_><<<grid, BX_ * BY_, 0, s>>>(B, B.dom, items, nitems, cur); \
+        return hipGetLastError();                                                   \
+    }
+    CAC_BPHASE(64, 8)
+    CAC_BPHASE(64, 4)
+    CAC_BPHASE(32, 8)
+    CAC_BPHASE(32, 16)
+    CAC_BPHASE(16, 16)
+    CAC_BPHASE(128, 4)
+#undef CAC_BPHASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_bvolume(const BatchPtrs &B, int nt, const uint2 *items, uint32_t nitems, uint32_t grid, int cur_next,
+                          hipStream_t s)
+{
+    k_bvol_finalize<<<B.ndom, 256, 0, s>>>(B, B.dom);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !nitems) return e;
+    switch (nt) {
+    case 128: k_bvol_apply<128><<<grid, 128, 0, s>>>(B, B.dom, items, nitems, cur_next); break;
+    case 256: k_bvol_apply<256><<<grid, 256, 0, s>>>(B, B.dom, items, nitems, cur_next); break;
+    case 512: k_bvol_apply<512><<<grid, 512, 0, s>>>(B, B.dom, items, nitems, cur_next); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int batch_blocks_per_cu(int kind, int code)
+{
+    int nb = 0;
+    hipError_t e = hipSuccess;
+    if (kind == 0) {
+        switch (code) {
+        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bhydro<128>, 128, 0); break;
+        case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bhydro<256>, 256, 0); break;
+        case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bhydro<512>, 512, 0); break;
+        default: return 0;
+        }
+    } else {
+        int bx, by;
+        phase_shape_of(code, bx, by);
+        if (bx == 64 && by == 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bphase<64, 8>, 512, 0);
+        else if (bx == 64 && by == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bphase<64, 4>, 256, 0);
+        else if (bx == 32 && by == 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bphase<32, 8>, 256, 0);
+        else if (bx == 32 && by == 16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bphase<32, 16>, 512, 0);
+        else if (bx == 16 && by == 16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bphase<16, 16>, 256, 0);
+        else if (bx == 128 && by == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bphase<128, 4>, 512, 0);
+        else return 0;
+    }
+    return e == hipSuccess ? nb : 0;
+}
+
+}  // namespace cac

@@ -73,6 +73,12 @@ struct Tiling {
     int phase;        // column tile code of the phase kernel (0 = automatic)
 };
 
+// Column tiling of the phase kernel: ntx x nty column tiles, z-chunks of zc planes.
+struct PhaseTiling {
+    int ntx, nty, nzc, zc;
+    uint32_t ntiles;
+};
+
 // Device buffers of one lattice (plain handle or one batched domain).
 struct Fields {
     float *f[2];        // post-collision populations, 27 planes each
@@ -91,6 +97,48 @@ struct Fields {
     float *pstar0;      // p* of the initial state (reported before the first step)
     int nwall;
 };
+
+// ---------------------------------------------------------------- batches
+// Device descriptor of one domain of a batch.  All domains live in shared
+// concatenated arrays; domain k's fields start at node offset `off` (its
+// populations at 27*off, vectors at 3*off) and keep the single-lattice layout.
+struct BatchDomain {
+    Grid g;
+    Tiling t;         // hydrodynamic tiling
+    PhaseTiling pt;   // phase tiling
+    DevParams p;
+    uint32_t off;     // node offset
+    uint32_t p_item0; // first FP64 partial of this domain's phase tiles
+};
+
+struct BatchPtrs {
+    float *f[2], *phi[2], *u, *a;
+    uint32_t *nbr;
+    uint8_t *solid;
+    int32_t *wall_idx;   // domain-local node index of each wall node
+    uint8_t *wall_q;
+    float *wall_n, *theta;
+    uint16_t *wall_dom;  // domain of each wall node
+    double2 *partial;    // per phase tile, at BatchDomain::p_item0 + tile
+    double *scal;        // 8 per domain: [0] M_target, [1] lambda, [2] M*, [3] W, [4] volume
+    uint32_t *flag;
+    const BatchDomain *dom;
+    int ndom;
+};
+
+// Work items of the persistent batched kernels: (domain, tile) pairs in the
+// order of the block schedule.  grid = number of persistent workgroups.
+hipError_t launch_bghost(const BatchPtrs &B, uint32_t nwall, int cur, hipStream_t s);
+hipError_t launch_bhydro(const BatchPtrs &B, int nt, const uint2 *items, uint32_t nitems, uint32_t grid, int cur,
+                         hipStream_t s);
+hipError_t launch_bphase(const BatchPtrs &B, int phase_code, const uint2 *items, uint32_t nitems, uint32_t grid,
+                         int cur, hipStream_t s);
+hipError_t launch_bvolume(const BatchPtrs &B, int nt, const uint2 *items, uint32_t nitems, uint32_t grid, int cur_next,
+                          hipStream_t s);
+// resident workgroups per CU of a batched kernel (kind 0 hydro / 1 phase), 0 on failure
+int batch_blocks_per_cu(int kind, int code);
+void phase_shape_of(int code, int &bx, int &by);  // code 1..6
+PhaseTiling phase_tiling(const Grid &g, int bx, int by);
 
 // ---------------------------------------------------------------- launchers
 // All enqueue on `s`; return the launch status.

@@ -41,6 +41,14 @@ struct cac_handle {
     std::string err;
 };
 
+namespace cac {
+DevParams make_dev_params(const cac_params &p);
+Tiling make_tiling(const Grid &g, int bx, int by, int bz);
+void build_geometry(const Grid &g, const uint8_t *solid, std::vector<uint32_t> &nbr, std::vector<int32_t> &widx,
+                    std::vector<int32_t> &wn6, std::vector<int32_t> &wdonor, int &nskip);
+bool valid_params(const cac_params &p);
+}  // namespace cac
+
 namespace {
 
 cac_status fail(cac_handle *h, cac_status s, const char *fmt, ...)
@@ -71,6 +79,16 @@ void *dev_alloc(cac_handle *h, size_t bytes)
     if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
     h->owned.push_back(p);
     return p;
+}
+
+}  // namespace
+
+namespace cac {
+
+bool valid_params(const cac_params &p)
+{
+    return p.rho_l > 0 && p.rho_g > 0 && p.nu_l > 0 && p.nu_g > 0 && p.delta > 0 && p.D >= 0 && p.sigma >= 0 &&
+           p.eps_phi >= 0 && p.eps_phi < 0.5;
 }
 
 DevParams make_dev_params(const cac_params &p)
@@ -190,6 +208,10 @@ void build_geometry(const Grid &g, const uint8_t *solid, std::vector<uint32_t> &
             }
 }
 
+}  // namespace cac
+
+namespace {
+
 cac_status run_step(cac_handle *h)
 {
     const int c = h->cur;
@@ -292,9 +314,7 @@ cac_status cac_init(cac_handle **hp, int nx, int ny, int nz, const cac_params *p
     if (nx < 2 || ny < 2 || nz < 2) return CAC_ERR_ARG;
     const unsigned long long N = (unsigned long long)nx * ny * nz;
     if (27ull * N >= (1ull << 31)) return CAC_ERR_ARG;
-    if (!(p->rho_l > 0 && p->rho_g > 0 && p->nu_l > 0 && p->nu_g > 0 && p->delta > 0 && p->D >= 0 &&
-          p->sigma >= 0 && p->eps_phi >= 0 && p->eps_phi < 0.5))
-        return CAC_ERR_ARG;
+    if (!valid_params(*p)) return CAC_ERR_ARG;
     cac_handle *h = new cac_handle();
     h->prm = *p;
     h->dp = make_dev_params(*p);

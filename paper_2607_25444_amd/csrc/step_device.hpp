@@ -1,0 +1,752 @@
+// step_device.hpp -- device bodies of the coupled step, shared by the
+// single-lattice kernels (kernels.hip) and the batched persistent kernels
+// (batch.hip).  Included only by HIP sources of libcac.
+#pragma once
+
+#include "cac_internal.hpp"
+
+namespace cac {
+
+// ------------------------------------------------------------------ helpers
+
+// Hardware dispatch sends workgroup b to XCD b % 8.  Re-number so that XCD k
+// owns a contiguous block of logical tiles (halo rows stay in its L2).
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n)
+{
+    const uint32_t k = b & 7u, j = b >> 3, q = n >> 3, r = n & 7u;
+    return k * q + (k < r ? k : r) + j;
+}
+
+struct Node {
+    int x, y, z;
+    bool in;
+};
+
+__device__ __forceinline__ Node tile_node(const Grid &g, const Tiling &t, uint32_t tile)
+{
+    const uint32_t txy = (uint32_t)t.tx * (uint32_t)t.ty;
+    const uint32_t tz = tile / txy;
+    const uint32_t r = tile - tz * txy;
+    const uint32_t ty = r / (uint32_t)t.tx;
+    const uint32_t tx = r - ty * (uint32_t)t.tx;
+    const int tid = threadIdx.x;
+    const int lx = tid % t.bx;
+    const int ly = (tid / t.bx) % t.by;
+    const int lz = tid / (t.bx * t.by);
+    Node nd;
+    nd.x = (int)tx * t.bx + lx;
+    nd.y = (int)ty * t.by + ly;
+    nd.z = (int)tz * t.bz + lz;
+    nd.in = nd.x < g.nx && nd.y < g.ny && nd.z < g.nz;
+    return nd;
+}
+
+// Periodic neighbour offsets along each axis: o[0] = coordinate - 1,
+// o[1] = coordinate, o[2] = coordinate + 1 (wrapped), already scaled by the
+// axis stride.
+struct Offs {
+    uint32_t x[3], y[3], z[3];
+};
+
+__device__ __forceinline__ Offs node_offsets(const Grid &g, int x, int y, int z)
+{
+    Offs o;
+    o.x[0] = (uint32_t)(x ? x - 1 : g.nx - 1);
+    o.x[1] = (uint32_t)x;
+    o.x[2] = (uint32_t)(x + 1 < g.nx ? x + 1 : 0);
+    o.y[0] = (uint32_t)(y ? y - 1 : g.ny - 1) * (uint32_t)g.nx;
+    o.y[1] = (uint32_t)y * (uint32_t)g.nx;
+    o.y[2] = (uint32_t)(y + 1 < g.ny ? y + 1 : 0) * (uint32_t)g.nx;
+    o.z[0] = (uint32_t)(z ? z - 1 : g.nz - 1) * g.nxny;
+    o.z[1] = (uint32_t)z * g.nxny;
+    o.z[2] = (uint32_t)(z + 1 < g.nz ? z + 1 : 0) * g.nxny;
+    return o;
+}
+
+template <int DX, int DY, int DZ>
+__device__ __forceinline__ uint32_t at(const Offs &o)
+{
+    return o.x[DX + 1] + o.y[DY + 1] + o.z[DZ + 1];
+}
+
+// 1-D smoothing weights of the D3Q27 tensor-product weights: w_i = t(cx)t(cy)t(cz)/216,
+// t(0) = 4, t(+-1) = 1.
+__host__ __device__ constexpr float tw(int d) { return d == 0 ? 4.0f : 1.0f; }
+
+// Isotropic gradient (Eq. (22)) and Laplacian (Eq. (23)) from a 3x3x3 stencil
+// s[k], k = (dz+1)*9 + (dy+1)*3 + (dx+1), in tensor-product form on the
+// differences d = s - s(0,0,0) (exact in FP32 for neighbouring values, so the
+// Laplacian does not lose digits to cancellation):
+//   grad_x = sum_{dy,dz} t(dy) t(dz) [d(+1,dy,dz) - d(-1,dy,dz)] / 72
+//   lap    = sum t(dx) t(dy) t(dz) d / 36
+__device__ __forceinline__ void stencil_grad_lap(const float (&s)[27], float &gx, float &gy, float &gz, float &lap)
+{
+    const float c0 = s[13];
+    float S[9];  // x-smoothed differences at (dy, dz)
+    gx = 0.f;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        const float m = s[3 * j] - c0, c = s[3 * j + 1] - c0, p = s[3 * j + 2] - c0;
+        S[j] = m + 4.0f * c + p;
+        const int dy = j % 3 - 1, dz = j / 3 - 1;
+        gx += tw(dy) * tw(dz) * (p - m);
+    }
+    gx *= (1.0f / 72.0f);
+    gy = 0.f;
+    gz = 0.f;
+    float l = 0.f;
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz) gy += tw(dz - 1) * (S[dz * 3 + 2] - S[dz * 3 + 0]);
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) gz += tw(dy - 1) * (S[6 + dy] - S[0 + dy]);
+#pragma unroll
+    for (int j = 0; j < 9; ++j) l += tw(j % 3 - 1) * tw(j / 3 - 1) * S[j];
+    gy *= (1.0f / 72.0f);
+    gz *= (1.0f / 72.0f);
+    lap = l * (1.0f / 36.0f);
+}
+
+// Hermite coefficients of a population set f_i = w_i [ps + 3 c.b + 4.5 H2:C2 + 4.5 H3:C3]
+// (c_s^2 = 1/3).  C3 is symmetric; only the 7 components that D3Q27 carries
+// (H3_aaa = 0 on the lattice) are stored.
+struct Herm {
+    float ps, bx, by, bz;
+    float xx, yy, zz, xy, xz, yz, tr3;  // C2 and trace(C2)/3
+    float xxy, xxz, yyx, yyz, zzx, zzy, xyz;
+};
+
+// Even and odd parts of f_i for the pair (i, opp(i)): f_i = E + O, f_opp = E - O.
+template <int I>
+__device__ __forceinline__ void herm_pair(const Herm &h, float &E, float &O)
+{
+    constexpr float cx = (float)Lat::cx[I], cy = (float)Lat::cy[I], cz = (float)Lat::cz[I];
+    constexpr float w = Lat::w(I);
+    const float ccc = cx * cx * h.xx + cy * cy * h.yy + cz * cz * h.zz +
+                      2.0f * (cx * cy * h.xy + cx * cz * h.xz + cy * cz * h.yz);
+    E = w * (h.ps + 4.5f * (ccc - h.tr3));
+    const float cb = cx * h.bx + cy * h.by + cz * h.bz;
+    constexpr float hx = cx * cx - 1.0f / 3.0f, hy = cy * cy - 1.0f / 3.0f, hz = cz * cz - 1.0f / 3.0f;
+    const float h3 = 3.0f * (hx * (cy * h.xxy + cz * h.xxz) + hy * (cx * h.yyx + cz * h.yyz) +
+                             hz * (cx * h.zzx + cy * h.zzy)) +
+                     6.0f * cx * cy * cz * h.xyz;
+    O = w * (3.0f * cb + 4.5f * h3);
+}
+
+// Single equilibrium population, Eq. (11): w [ps + 3 cu + 4.5 ((cu)^2 - u^2/3) + 4.5 ((cu)^3 - cu u^2)]
+template <int I>
+__device__ __forceinline__ float feq_one(float ps, float ux, float uy, float uz)
+{
+    constexpr float cx = (float)Lat::cx[I], cy = (float)Lat::cy[I], cz = (float)Lat::cz[I];
+    const float cu = cx * ux + cy * uy + cz * uz;
+    const float uu = ux * ux + uy * uy + uz * uz;
+    return Lat::w(I) * (ps + 3.0f * cu + 4.5f * (cu * cu - uu * (1.0f / 3.0f)) + 4.5f * (cu * cu * cu - cu * uu));
+}
+
+// ------------------------------------------------------------------ W: ghosts
+
+// One thread per wall node b (Sec. II B, the ghost-node update):
+//   donor x_f = b + c_q*, phi_f and the isotropic gradient at x_f (fluid
+//   stencil points from the current buffer, wall points from the previous
+//   ghosts in the other buffer: Jacobi), tangential gradient (Eq. (42)),
+//   theta_c = pi - theta (Eq. (43)), normal derivative (Eq. (44)), corrected
+//   gradient (Eq. (45)), lambda_s (Eq. (47)), ghost (Eq. (46)) written to the
+//   current buffer.  Reads only fluid data and old ghosts, writes only b.
+__device__ __forceinline__ void ghost_node(const Grid &g, const DevParams &p, int k, const int32_t *__restrict__ widx,
+                                           const uint8_t *__restrict__ wq, const float *__restrict__ wn,
+                                           const float *__restrict__ theta, float *phi_cur,
+                                           const float *__restrict__ phi_old, const uint32_t *__restrict__ nbr,
+                                           float *__restrict__ a)
+{
+    const int q = wq[k];
+    if (q >= 27) return;  // skipped node: ghost keeps its value
+    const uint32_t b = (uint32_t)widx[k];
+    const int bx = (int)(b % (uint32_t)g.nx);
+    const int by = (int)((b / (uint32_t)g.nx) % (uint32_t)g.ny);
+    const int bz = (int)(b / g.nxny);
+    int cxq = 0, cyq = 0, czq = 0;
+    static_for<27>([&](auto I) {
+        if (q == I) {
+            cxq = Lat::cx[I];
+            cyq = Lat::cy[I];
+            czq = Lat::cz[I];
+        }
+    });
+    int fx = bx + cxq, fy = by + cyq, fz = bz + czq;
+    fx = fx < 0 ? fx + g.nx : (fx >= g.nx ? fx - g.nx : fx);
+    fy = fy < 0 ? fy + g.ny : (fy >= g.ny ? fy - g.ny : fy);
+    fz = fz < 0 ? fz + g.nz : (fz >= g.nz ? fz - g.nz : fz);
+    const Offs o = node_offsets(g, fx, fy, fz);
+    const uint32_t m = nbr[at<0, 0, 0>(o)];
+    float s[27];
+    static_for<27>([&](auto K) {
+        constexpr int kk = K;
+        constexpr int dx = kk % 3 - 1, dy = (kk / 3) % 3 - 1, dz = kk / 9 - 1;
+        constexpr int li = Lat::idx(dx, dy, dz);
+        const uint32_t id = at<dx, dy, dz>(o);
+        s[kk] = ((m >> li) & 1u) ? phi_old[id] : phi_cur[id];
+    });
+    float gx, gy, gz, lap;
+    stencil_grad_lap(s, gx, gy, gz, lap);
+    const float phif = s[13];
+    const float nx = wn[3 * k], ny = wn[3 * k + 1], nz = wn[3 * k + 2];
+    const float gn = gx * nx + gy * ny + gz * nz;
+    const float px = gx - gn * nx, py = gy - gn * ny, pz = gz - gn * nz;
+    const float t = sqrtf(px * px + py * py + pz * pz);
+    const float thc = 3.14159265358979f - theta[k];
+    float sn, cs;
+    sincosf(thc, &sn, &cs);
+    const float cot = (fabsf(sn) < p.sin_tol) ? copysignf(p.cot_max, cs) : cs / sn;
+    const float dn = -t * cot;
+    const float cgx = px + dn * nx, cgy = py + dn * ny, cgz = pz + dn * nz;
+    const float l2 = 4.0f * phif * (1.0f - phif);
+    const float lam = sqrtf(l2 > 0.0f ? l2 : 0.0f);
+    const float gv = phif - lam * (cgx * (float)cxq + cgy * (float)cyq + cgz * (float)czq);
+    phi_cur[b] = gv;
+    if (p.wall_compression) {
+        const float c2 = cgx * cgx + cgy * cgy + cgz * cgz;
+        float ax = 0.f, ay = 0.f, az = 0.f;
+        if (c2 > p.eps_n2) {
+            const float sc = gv * (1.0f - gv) * rsqrtf(c2);
+            ax = sc * cgx;
+            ay = sc * cgy;
+            az = sc * cgz;
+        }
+        a[b] = ax;
+        a[g.N + b] = ay;
+        a[2u * g.N + b] = az;
+    }
+}
+
+// ------------------------------------------------------------------ H: hydro
+
+// Fused pull collide-stream at fluid node x (Sec. II A):
+//   pull f_i(x) = f*_i(x - c_i), or f*_opp(i)(x) when x - c_i is solid
+//   (halfway bounce-back); phi stencil -> grad, lap (Eqs. (22)-(23));
+//   mu_phi and F_sigma (Eq. (19)); mixture laws (Eqs. (8)-(10)); moments
+//   (Eqs. (6)-(7)); F_p (Eq. (20)), F_ext, F_nu (Eq. (21)); third-order
+//   equilibrium (Eq. (11)), Guo forcing (Eq. (17)) with the trapezoidal shift,
+//   recursive regularisation (Eqs. (14), (16)):
+//     f*_i = w_i [p* + 3 c.(u + a/2) + 4.5 H2:C2 + 4.5 H3:C3],
+//     C2 = uu + (ua + au)/2 + (1 - omega) A2,  C3 = uuu + (1 - omega) S(u A2),
+//     A2 = P - p*/3 I - uu + (ua + au)/2  (second moment of f - f^eq + S/2).
+//   Writes f* and u.
+__device__ __forceinline__ void hydro_node(const Grid &g, const DevParams &p, const Node &nd,
+                                           const float *__restrict__ fin, float *__restrict__ fout,
+                                           const float *__restrict__ phi, const uint32_t *__restrict__ nbr,
+                                           float *__restrict__ u, uint32_t *__restrict__ flag)
+{
+    if (!nd.in) return;
+    const Offs o = node_offsets(g, nd.x, nd.y, nd.z);
+    const uint32_t n = at<0, 0, 0>(o);
+    const uint32_t m = nbr[n];
+    if (m & 1u) return;
+    const uint32_t N = g.N;
+
+    float s[27];
+    static_for<27>([&](auto K) {
+        constexpr int kk = K;
+        s[kk] = phi[at<kk % 3 - 1, (kk / 3) % 3 - 1, kk / 9 - 1>(o)];
+    });
+    float f[27];
+    static_for<27>([&](auto I) {
+        constexpr int i = I;
+        if constexpr (i == 0) {
+            f[0] = fin[n];
+        } else {
+            constexpr int ob = Lat::opp(i);
+            const uint32_t src = at<Lat::cx[ob], Lat::cy[ob], Lat::cz[ob]>(o);  // x - c_i
+            const bool wall = (m >> ob) & 1u;
+            f[i] = fin[wall ? (uint32_t)ob * N + n : (uint32_t)i * N + src];
+        }
+    });
+
+    float gx, gy, gz, lap;
+    stencil_grad_lap(s, gx, gy, gz, lap);
+    const float ph = s[13];
+
+    // kinetic moments
+    float ps = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+    float Pxx = 0.f, Pyy = 0.f, Pzz = 0.f, Pxy = 0.f, Pxz = 0.f, Pyz = 0.f;
+    static_for<27>([&](auto I) {
+        constexpr int i = I;
+        constexpr float cx = (float)Lat::cx[i], cy = (float)Lat::cy[i], cz = (float)Lat::cz[i];
+        const float v = f[i];
+        ps += v;
+        if constexpr (Lat::cx[i] != 0) { jx += cx * v; Pxx += v; }
+        if constexpr (Lat::cy[i] != 0) { jy += cy * v; Pyy += v; }
+        if constexpr (Lat::cz[i] != 0) { jz += cz * v; Pzz += v; }
+        if constexpr (Lat::cx[i] * Lat::cy[i] != 0) Pxy += cx * cy * v;
+        if constexpr (Lat::cx[i] * Lat::cz[i] != 0) Pxz += cx * cz * v;
+        if constexpr (Lat::cy[i] * Lat::cz[i] != 0) Pyz += cy * cz * v;
+    });
+
+    // chemical potential, capillary force, mixture properties
+    const float mu_phi = p.beta4 * ph * (ph - 1.0f) * (ph - 0.5f) - p.kappa_phi * lap;
+    float Fx = mu_phi * gx, Fy = mu_phi * gy, Fz = mu_phi * gz;
+    const float rho = p.rho_g + p.drho * ph;
+    const float irho = 1.0f / rho;
+    const float nu = (p.mu_g + p.dmu * ph) * irho;
+    const float omega = 1.0f / (0.5f + 3.0f * nu);
+    float ax, ay, az;
+    if (p.variable_density) {
+        const float grx = p.drho * gx, gry = p.drho * gy, grz = p.drho * gz;
+        const float cp = -ps * (1.0f / 3.0f);
+        const float fe = p.drho * ph;
+        Fx += cp * grx + fe * p.gx;
+        Fy += cp * gry + fe * p.gy;
+        Fz += cp * grz + fe * p.gz;
+        const float a1x = Fx * irho, a1y = Fy * irho, a1z = Fz * irho;
+        const float ux1 = jx + 0.5f * a1x, uy1 = jy + 0.5f * a1y, uz1 = jz + 0.5f * a1z;
+        const float p3 = ps * (1.0f / 3.0f);
+        const float Qxx = Pxx - p3 - ux1 * ux1, Qyy = Pyy - p3 - uy1 * uy1, Qzz = Pzz - p3 - uz1 * uz1;
+        const float Qxy = Pxy - ux1 * uy1, Qxz = Pxz - ux1 * uz1, Qyz = Pyz - uy1 * uz1;
+        const float cnu = -3.0f * nu * omega * irho;
+        ax = a1x + cnu * (Qxx * grx + Qxy * gry + Qxz * grz);
+        ay = a1y + cnu * (Qxy * grx + Qyy * gry + Qyz * grz);
+        az = a1z + cnu * (Qxz * grx + Qyz * gry + Qzz * grz);
+    } else {
+        ax = Fx * irho;
+        ay = Fy * irho;
+        az = Fz * irho;
+    }
+    const float ux = jx + 0.5f * ax, uy = jy + 0.5f * ay, uz = jz + 0.5f * az;
+
+    // A2 (R2 reading: local second moment of f - f^eq + S/2)
+    const float p3 = ps * (1.0f / 3.0f);
+    const float A2xx = Pxx - p3 - ux * ux + ux * ax;
+    const float A2yy = Pyy - p3 - uy * uy + uy * ay;
+    const float A2zz = Pzz - p3 - uz * uz + uz * az;
+    const float A2xy = Pxy - ux * uy + 0.5f * (ux * ay + ax * uy);
+    const float A2xz = Pxz - ux * uz + 0.5f * (ux * az + ax * uz);
+    const float A2yz = Pyz - uy * uz + 0.5f * (uy * az + ay * uz);
+    const float om1 = 1.0f - omega;
+
+    Herm h;
+    h.ps = ps;
+    h.bx = ux + 0.5f * ax;
+    h.by = uy + 0.5f * ay;
+    h.bz = uz + 0.5f * az;
+    h.xx = ux * ux + ux * ax + om1 * A2xx;
+    h.yy = uy * uy + uy * ay + om1 * A2yy;
+    h.zz = uz * uz + uz * az + om1 * A2zz;
+    h.xy = ux * uy + 0.5f * (ux * ay + ax * uy) + om1 * A2xy;
+    h.xz = ux * uz + 0.5f * (ux * az + ax * uz) + om1 * A2xz;
+    h.yz = uy * uz + 0.5f * (uy * az + ay * uz) + om1 * A2yz;
+    h.tr3 = (h.xx + h.yy + h.zz) * (1.0f / 3.0f);
+    // C3 = uuu + (1 - omega)(u_a A2_bg + u_b A2_ag + u_g A2_ab)
+    h.xxy = ux * ux * uy + om1 * (2.0f * ux * A2xy + uy * A2xx);
+    h.xxz = ux * ux * uz + om1 * (2.0f * ux * A2xz + uz * A2xx);
+    h.yyx = uy * uy * ux + om1 * (2.0f * uy * A2xy + ux * A2yy);
+    h.yyz = uy * uy * uz + om1 * (2.0f * uy * A2yz + uz * A2yy);
+    h.zzx = uz * uz * ux + om1 * (2.0f * uz * A2xz + ux * A2zz);
+    h.zzy = uz * uz * uy + om1 * (2.0f * uz * A2yz + uy * A2zz);
+    h.xyz = ux * uy * uz + om1 * (ux * A2yz + uy * A2xz + uz * A2xy);
+
+    fout[n] = Lat::w(0) * (h.ps - 4.5f * h.tr3);
+    static_for<13>([&](auto P) {
+        constexpr int i = 2 * P + 1;
+        float E, O;
+        herm_pair<i>(h, E, O);
+        fout[(uint32_t)i * N + n] = E + O;
+        fout[(uint32_t)(i + 1) * N + n] = E - O;
+    });
+
+    u[n] = ux;
+    u[N + n] = uy;
+    u[2u * N + n] = uz;
+    if (!(isfinite(ux) && isfinite(uy) && isfinite(uz) && isfinite(ps))) flag[0] = 1u;
+}
+
+// ------------------------------------------------------------------ P: CAC
+
+__device__ __forceinline__ float minmod(float a, float b)
+{
+    // Eq. (32)
+    return (a * b <= 0.0f) ? 0.0f : (a > 0.0f ? fminf(a, b) : fmaxf(a, b));
+}
+
+// Face flux between nodes L and R (R = L + e_d), Eqs. (30)-(34):
+// u_f = (u_L + u_R)/2, minmod slopes at L and R, upwind reconstruction.
+__device__ __forceinline__ float muscl_flux(float pLL, float pL, float pR, float pRR, float uL, float uR)
+{
+    const float uf = 0.5f * (uL + uR);
+    const float sL = minmod(pL - pLL, pR - pL);
+    const float sR = minmod(pR - pL, pRR - pR);
+    return uf * (uf >= 0.0f ? pL + 0.5f * sL : pR - 0.5f * sR);
+}
+
+template <int NT>
+__device__ __forceinline__ void block_sum2(double &x, double &y)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        x += __shfl_xor(x, off, 64);
+        y += __shfl_xor(y, off, 64);
+    }
+    __shared__ double sx[NT / 64], sy[NT / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        sx[wid] = x;
+        sy[wid] = y;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tx = 0.0, ty = 0.0;
+#pragma unroll
+        for (int k = 0; k < NT / 64; ++k) {
+            tx += sx[k];
+            ty += sy[k];
+        }
+        x = tx;
+        y = ty;
+    }
+}
+
+// CAC update (Eq. (28)) as a 2.5-D stencil: a workgroup owns a BX x BY
+// column tile and marches up a chunk of ZC planes.  LDS holds a ring of five
+// phi planes (z-2..z+2, halo 2 in x and y) and a ring of three planes of the
+// compressive flux a = phi(1-phi) grad/|grad| (z-1..z+1, halo 1) together
+// with the solid flags.  At each plane: load phi(z+2), build a(z+1) from the
+// isotropic gradient (Eq. (22), normal of Eq. (25)), then update the nodes of
+// plane z:
+//   phi* = phi - div(F_a) + D lap(phi) - kappa div_iso(a)
+// with MUSCL-minmod face fluxes (Eqs. (29)-(34)), zero on faces touching a
+// solid node, and div_iso with the weights w_i/c_s^2.  On solid nodes a is
+// the value the ghost update assigned (zero unless wall_compression is on).
+// Each thread also accumulates sum(phi*) and sum(chi) (Eqs. (49), (51)) in
+// FP64; the workgroup writes one partial per tile.
+__device__ __forceinline__ int wrapc(int v, int n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// Per-plane partial sums of the tensor-product stencils on a 3x3 plane patch
+// v[3*(dy+1) + (dx+1)] around a column:
+//   sx = sum_dy t(dy) [v(+1,dy) - v(-1,dy)]   (x differences smoothed in y)
+//   sy = sum_dx t(dx) [v(dx,+1) - v(dx,-1)]
+//   tq = sum t(dx) t(dy) [v - v(0,0)]          (smoothed, relative to the centre)
+// A column's gradient and Laplacian over planes -1, 0, +1 follow as
+//   grad_x = (sx_- + 4 sx_0 + sx_+)/72, grad_y likewise with sy,
+//   grad_z = (tq_+ - tq_- + 36 (c_+ - c_-))/72,
+//   lap    = (tq_- + 4 tq_0 + tq_+ + 36 (c_- + c_+ - 2 c_0))/36,
+// the same sums as Eqs. (22)-(23), regrouped plane by plane.
+struct PlaneSums {
+    float sx, sy, tq, c;
+};
+
+__device__ __forceinline__ PlaneSums plane_sums(const float (&v)[9])
+{
+    PlaneSums r;
+    r.c = v[4];
+    r.sx = (v[2] - v[0]) + 4.0f * (v[5] - v[3]) + (v[8] - v[6]);
+    r.sy = (v[6] - v[0]) + 4.0f * (v[7] - v[1]) + (v[8] - v[2]);
+    r.tq = (v[0] - r.c) + (v[2] - r.c) + (v[6] - r.c) + (v[8] - r.c) +
+           4.0f * ((v[1] - r.c) + (v[3] - r.c) + (v[5] - r.c) + (v[7] - r.c));
+    return r;
+}
+
+// minmod of Eq. (32) in branch-free form: equal to 0 when ab <= 0, else the
+// argument of smaller magnitude.
+__device__ __forceinline__ float minmod2(float a, float b)
+{
+    return fmaxf(fminf(a, b), 0.0f) + fminf(fmaxf(a, b), 0.0f);
+}
+
+// The two face fluxes of a node along one axis from phi at offsets -2..+2 and
+// the axial velocity at -1, 0, +1 (Eqs. (30)-(34)); the slope at the node is
+// shared by both faces.  open_m/open_p: the face does not touch a solid node.
+__device__ __forceinline__ float muscl_axis(float q0, float q1, float q2, float q3, float q4, float um, float uc,
+                                            float up, bool open_m, bool open_p)
+{
+    const float d0 = q1 - q0, d1 = q2 - q1, d2 = q3 - q2, d3 = q4 - q3;
+    const float sm = minmod2(d0, d1), sc = minmod2(d1, d2), sp = minmod2(d2, d3);
+    const float ufp = 0.5f * (uc + up), ufm = 0.5f * (um + uc);
+    const float fp = ufp * (ufp >= 0.0f ? q2 + 0.5f * sc : q3 - 0.5f * sp);
+    const float fm = ufm * (ufm >= 0.0f ? q1 + 0.5f * sm : q2 - 0.5f * sc);
+    return (open_p ? fp : 0.0f) - (open_m ? fm : 0.0f);
+}
+
+// One (column tile, z-chunk) of the phase update; the workgroup's FP64 sums
+// go to *partial_out (written by thread 0).  Must be entered by the whole
+// workgroup; reuses its LDS on every call.
+template <int BX, int BY>
+__device__ __forceinline__ void phase_tile(const Grid &g, const PhaseTiling &pt, const DevParams &p, uint32_t tile,
+                                           const float *__restrict__ phi, float *__restrict__ phi_out,
+                                           const float *__restrict__ u, const float *__restrict__ aw,
+                                           const uint8_t *__restrict__ solid, double2 *partial_out,
+                                           uint32_t *__restrict__ flag)
+{
+    constexpr int NT = BX * BY;
+    constexpr int HX = BX + 4, HY = BY + 4;  // phi plane, halo 2
+    constexpr int AX = BX + 2, AY = BY + 2;  // flux / flag plane, halo 1
+    constexpr int PF = (HX * HY + NT - 1) / NT;  // phi values per thread per plane
+    constexpr int PA = (AX * AY + NT - 1) / NT;  // flux points per thread per plane
+    __shared__ float sphi[5][HY][HX];
+    __shared__ float sa[3][3][AY][AX];
+    __shared__ uint8_t ssol[3][AY][AX];
+
+    const int tcx = (int)(tile % (uint32_t)pt.ntx);
+    const int tcy = (int)((tile / (uint32_t)pt.ntx) % (uint32_t)pt.nty);
+    const int tcz = (int)(tile / ((uint32_t)pt.ntx * (uint32_t)pt.nty));
+    const int x0 = tcx * BX, y0 = tcy * BY, z0 = tcz * pt.zc;
+    const int z1 = min(z0 + pt.zc, g.nz);
+    const int tid = threadIdx.x;
+    const int lx = tid % BX, ly = tid / BX;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool col_in = x < g.nx && y < g.ny;
+    const uint32_t N = g.N;
+
+    auto pslot = [&](int zz) { return (zz - z0 + 10) % 5; };
+    auto aslot = [&](int zz) { return (zz - z0 + 3) % 3; };
+    auto zoff = [&](int zz) { return (uint32_t)wrapc(zz, g.nz) * g.nxny; };
+
+    // this thread's share of the halo planes: global in-plane offset and LDS position
+    uint32_t pxy[PF], axy[PA];
+    int apos[PA];
+#pragma unroll
+    for (int r = 0; r < PF; ++r) {
+        const int k = tid + r * NT;
+        const int hx = k % HX, hy = k / HX;
+        pxy[r] = k < HX * HY ? (uint32_t)wrapc(x0 - 2 + hx, g.nx) + (uint32_t)wrapc(y0 - 2 + hy, g.ny) * (uint32_t)g.nx : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < PA; ++r) {
+        const int k = tid + r * NT;
+        const int ax = k % AX, ay = k / AX;
+        axy[r] = k < AX * AY ? (uint32_t)wrapc(x0 - 1 + ax, g.nx) + (uint32_t)wrapc(y0 - 1 + ay, g.ny) * (uint32_t)g.nx : 0u;
+        apos[r] = k < AX * AY ? ay * AX + ax : -1;
+    }
+    auto fetch_phi = [&](int zz, float (&v)[PF]) {
+        const uint32_t zo = zoff(zz);
+#pragma unroll
+        for (int r = 0; r < PF; ++r)
+            if (tid + r * NT < HX * HY) v[r] = phi[pxy[r] + zo];
+    };
+    auto store_phi = [&](int zz, const float (&v)[PF]) {
+        float *dst = &sphi[pslot(zz)][0][0];
+#pragma unroll
+        for (int r = 0; r < PF; ++r)
+            if (tid + r * NT < HX * HY) dst[tid + r * NT] = v[r];
+    };
+    auto fetch_sol = [&](int zz, uint8_t (&v)[PA]) {
+        const uint32_t zo = zoff(zz);
+#pragma unroll
+        for (int r = 0; r < PA; ++r)
+            if (apos[r] >= 0) v[r] = solid[axy[r] + zo];
+    };
+    auto store_sol = [&](int zz, const uint8_t (&v)[PA]) {
+        uint8_t *dst = &ssol[aslot(zz)][0][0];
+#pragma unroll
+        for (int r = 0; r < PA; ++r)
+            if (apos[r] >= 0) dst[apos[r]] = v[r];
+    };
+    // 3x3 patch of phi plane zz centred on halo-1 position (ax, ay) (= halo-2 position + 1)
+    auto patch = [&](int zz, int ax, int ay, float (&v)[9]) {
+        const float *pl = &sphi[pslot(zz)][0][0];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) v[j] = pl[(ay + j / 3) * HX + ax + j % 3];
+    };
+
+    // rolling plane sums of every flux point this thread builds (planes zz-1, zz)
+    PlaneSums bprev[PA], bcur[PA];
+    auto flux_points_sums = [&](int zz, PlaneSums (&out)[PA]) {
+#pragma unroll
+        for (int r = 0; r < PA; ++r) {
+            if (apos[r] < 0) continue;
+            float v[9];
+            patch(zz, apos[r] % AX, apos[r] / AX, v);
+            out[r] = plane_sums(v);
+        }
+    };
+    // compressive flux plane zz: needs phi planes zz-1..zz+1 (sums of zz-1, zz rolled in)
+    auto build_a = [&](int zz) {
+        const int sl = aslot(zz);
+        const uint32_t zo = zoff(zz);
+        PlaneSums nxt[PA];
+        flux_points_sums(zz + 1, nxt);
+#pragma unroll
+        for (int r = 0; r < PA; ++r) {
+            if (apos[r] < 0) continue;
+            const int pos = apos[r];
+            float cx = 0.f, cy = 0.f, cz = 0.f;
+            if ((&ssol[sl][0][0])[pos]) {
+                if (p.wall_compression) {
+                    const uint32_t id = axy[r] + zo;
+                    cx = aw[id];
+                    cy = aw[N + id];
+                    cz = aw[2u * N + id];
+                }
+            } else {
+                const PlaneSums &m = bprev[r], &c = bcur[r], &q = nxt[r];
+                const float gx = (m.sx + 4.0f * c.sx + q.sx) * (1.0f / 72.0f);
+                const float gy = (m.sy + 4.0f * c.sy + q.sy) * (1.0f / 72.0f);
+                const float gz = (q.tq - m.tq + 36.0f * (q.c - m.c)) * (1.0f / 72.0f);
+                const float g2 = gx * gx + gy * gy + gz * gz;
+                if (g2 > p.eps_n2) {
+                    const float sc = c.c * (1.0f - c.c) * rsqrtf(g2);
+                    cx = sc * gx;
+                    cy = sc * gy;
+                    cz = sc * gz;
+                }
+            }
+            (&sa[sl][0][0][0])[pos] = cx;
+            (&sa[sl][1][0][0])[pos] = cy;
+            (&sa[sl][2][0][0])[pos] = cz;
+            bprev[r] = bcur[r];
+            bcur[r] = nxt[r];
+        }
+    };
+
+    // velocities this node's fluxes need on plane zz
+    const uint32_t cxy = col_in ? (uint32_t)x + (uint32_t)y * (uint32_t)g.nx : 0u;
+    const uint32_t xm = col_in ? (uint32_t)wrapc(x - 1, g.nx) + (uint32_t)y * (uint32_t)g.nx : 0u;
+    const uint32_t xp = col_in ? (uint32_t)wrapc(x + 1, g.nx) + (uint32_t)y * (uint32_t)g.nx : 0u;
+    const uint32_t ym = col_in ? (uint32_t)x + (uint32_t)wrapc(y - 1, g.ny) * (uint32_t)g.nx : 0u;
+    const uint32_t yp = col_in ? (uint32_t)x + (uint32_t)wrapc(y + 1, g.ny) * (uint32_t)g.nx : 0u;
+    struct UPlane {
+        float xm, xc, xp, ym, yc, yp, zn;  // zn: u_z one plane up
+    };
+    auto fetch_u = [&](int zz, UPlane &v) {
+        if (!col_in) return;
+        const uint32_t zo = zoff(zz);
+        v.xm = u[xm + zo];
+        v.xc = u[cxy + zo];
+        v.xp = u[xp + zo];
+        v.ym = u[N + ym + zo];
+        v.yc = u[N + cxy + zo];
+        v.yp = u[N + yp + zo];
+        v.zn = u[2u * N + cxy + zoff(zz + 1)];
+    };
+
+    const int hx = lx + 2, hy = ly + 2, ax = lx + 1, ay = ly + 1;
+    // column-rolling sums of the output node: Laplacian sums (tq, c) of planes, the
+    // in-plane cross of plane z, and the flux-divergence plane sums
+    auto col_patch = [&](int zz, float (&v)[9]) { patch(zz, lx + 1, ly + 1, v); };
+    auto flux_sums = [&](int zz, float &X, float &Y, float &Z) {
+        const int sl = aslot(zz);
+        const float *fx = &sa[sl][0][0][0], *fy = &sa[sl][1][0][0], *fz = &sa[sl][2][0][0];
+        const int c0 = ay * AX + ax;
+        X = (fx[c0 - AX + 1] - fx[c0 - AX - 1]) + 4.0f * (fx[c0 + 1] - fx[c0 - 1]) + (fx[c0 + AX + 1] - fx[c0 + AX - 1]);
+        Y = (fy[c0 + AX - 1] - fy[c0 - AX - 1]) + 4.0f * (fy[c0 + AX] - fy[c0 - AX]) + (fy[c0 + AX + 1] - fy[c0 - AX + 1]);
+        Z = fz[c0 - AX - 1] + fz[c0 - AX + 1] + fz[c0 + AX - 1] + fz[c0 + AX + 1] +
+            4.0f * (fz[c0 - AX] + fz[c0 - 1] + fz[c0 + 1] + fz[c0 + AX]) + 16.0f * fz[c0];
+    };
+
+    // prologue: phi planes z0-2..z0+1, flags z0-1, z0, flux planes z0-1, z0
+    {
+        float v[PF];
+        uint8_t f8[PA];
+        for (int zz = z0 - 2; zz <= z0 + 1; ++zz) {
+            fetch_phi(zz, v);
+            store_phi(zz, v);
+        }
+        for (int zz = z0 - 1; zz <= z0; ++zz) {
+            fetch_sol(zz, f8);
+            store_sol(zz, f8);
+        }
+    }
+    __syncthreads();
+    flux_points_sums(z0 - 2, bprev);
+    flux_points_sums(z0 - 1, bcur);
+    build_a(z0 - 1);
+    build_a(z0);
+    __syncthreads();
+    // output column state for plane z0
+    float tq_m, tq_c, c_m2, c_m, c_c, cr_xm, cr_xp, cr_ym, cr_yp, X_m, X_c, Y_m, Y_c, Z_m, Z_c;
+    {
+        float v[9];
+        col_patch(z0 - 1, v);
+        const PlaneSums sm = plane_sums(v);
+        col_patch(z0, v);
+        const PlaneSums sc = plane_sums(v);
+        tq_m = sm.tq;
+        c_m = sm.c;
+        tq_c = sc.tq;
+        c_c = sc.c;
+        cr_xm = v[3];
+        cr_xp = v[5];
+        cr_ym = v[1];
+        cr_yp = v[7];
+        c_m2 = sphi[pslot(z0 - 2)][hy][hx];
+        flux_sums(z0 - 1, X_m, Y_m, Z_m);
+        flux_sums(z0, X_c, Y_c, Z_c);
+    }
+    float nphi[PF];
+    uint8_t nsol[PA];
+    UPlane uc{}, un{};
+    float uzm = 0.f, uzc = 0.f, uzp = 0.f;
+    fetch_phi(z0 + 2, nphi);
+    fetch_sol(z0 + 1, nsol);
+    fetch_u(z0, uc);
+    if (col_in) {
+        uzm = u[2u * N + cxy + zoff(z0 - 1)];
+        uzc = u[2u * N + cxy + zoff(z0)];
+    }
+    uzp = uc.zn;
+
+    double sphis = 0.0, schi = 0.0;
+    for (int z = z0; z < z1; ++z) {
+        __syncthreads();  // the previous plane is done with the slots overwritten below
+        store_phi(z + 2, nphi);
+        store_sol(z + 1, nsol);
+        if (z + 1 < z1) {  // prefetch for the next plane; lands while this one computes
+            fetch_phi(z + 3, nphi);
+            fetch_sol(z + 2, nsol);
+            fetch_u(z + 1, un);
+        }
+        __syncthreads();
+        build_a(z + 1);
+        __syncthreads();
+        // new column sums of plane z+1 (phi) and flux plane z+1
+        float v[9];
+        col_patch(z + 1, v);
+        const PlaneSums sp = plane_sums(v);
+        float X_p, Y_p, Z_p;
+        flux_sums(z + 1, X_p, Y_p, Z_p);
+        const int sa_c = aslot(z);
+        const uint8_t *fl = &ssol[sa_c][0][0];
+        const int c0 = ay * AX + ax;
+        if (col_in && !fl[c0]) {
+            const float ph = c_c;
+            const float lap = (tq_m + 4.0f * tq_c + sp.tq + 36.0f * ((c_m - ph) + (sp.c - ph))) * (1.0f / 36.0f);
+            const float *p0 = &sphi[pslot(z)][0][0];
+            const int h0 = hy * HX + hx;
+            const float c_p2 = sphi[pslot(z + 2)][hy][hx];
+            float div_a = muscl_axis(p0[h0 - 2], cr_xm, ph, cr_xp, p0[h0 + 2], uc.xm, uc.xc, uc.xp, !fl[c0 - 1], !fl[c0 + 1]);
+            div_a += muscl_axis(p0[h0 - 2 * HX], cr_ym, ph, cr_yp, p0[h0 + 2 * HX], uc.ym, uc.yc, uc.yp, !fl[c0 - AX],
+                                !fl[c0 + AX]);
+            div_a += muscl_axis(c_m2, c_m, ph, sp.c, c_p2, uzm, uzc, uzp, !ssol[aslot(z - 1)][ay][ax], !ssol[aslot(z + 1)][ay][ax]);
+            const float div_c = (X_m + 4.0f * X_c + X_p + Y_m + 4.0f * Y_c + Y_p + Z_p - Z_m) * (1.0f / 72.0f);
+            const float ps = ph - div_a + p.D * lap - p.kappa * div_c;
+            phi_out[cxy + (uint32_t)z * g.nxny] = ps;
+            if (!isfinite(ps)) flag[0] = 1u;
+            sphis += (double)ps;
+            if (ps > p.eps_phi && ps < 1.0f - p.eps_phi) schi += (double)ps * (1.0 - (double)ps);
+        }
+        // roll the column state to plane z+1
+        tq_m = tq_c;
+        tq_c = sp.tq;
+        c_m2 = c_m;
+        c_m = c_c;
+        c_c = sp.c;
+        cr_xm = v[3];
+        cr_xp = v[5];
+        cr_ym = v[1];
+        cr_yp = v[7];
+        X_m = X_c;
+        X_c = X_p;
+        Y_m = Y_c;
+        Y_c = Y_p;
+        Z_m = Z_c;
+        Z_c = Z_p;
+        uc = un;
+        uzm = uzc;
+        uzc = uzp;
+        uzp = un.zn;
+    }
+    block_sum2<NT>(sphis, schi);
+    if (tid == 0) *partial_out = make_double2(sphis, schi);
+}
+
+}  // namespace cac

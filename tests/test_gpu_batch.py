@@ -1,0 +1,135 @@
+"""Batched persistent step (libcac cac_batch_*) on the GPU: every domain equals
+the same domain advanced alone, and the FP64 oracle; schedules, graph replay
+and the autotuner leave results unchanged."""
+import numpy as np
+import pytest
+
+from paper_2607_25444_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _domains():
+    a = W.sessile((24, 20, 16), 5.0, 45.0)
+    b = W.sessile((32, 32, 24), 7.0, 120.0, centre_z=7.5)
+    shape = (40, 36, 20)
+    c = W.Workload("vardens", shape, W.random_geometry(shape, 5, n_blocks=3), W.uniform_theta(shape, 80.0),
+                   W.tanh_droplet(shape, (19.5, 17.5, 9.0), 6.0, 4.0).astype(np.float32),
+                   W.default_params(rho_l=1.2, rho_g=0.9, nu_l=0.031, nu_g=0.24, sigma=0.025, g=(0, 0, -1e-5)), 0)
+    d = W.sessile((48, 16, 12), 4.0, 100.0)
+    return [a, b, c, d]
+
+
+def _single(w, steps):
+    from paper_2607_25444_amd import capi
+    s = capi.Sim(w.shape, w.params)
+    s.set_geometry(w.solid, w.theta)
+    s.set_state(w.phi0)
+    s.step(steps)
+    phi, u, ps = s.fields()
+    s.sync()
+    out = phi.cpu().numpy().astype(np.float64), u.cpu().numpy().astype(np.float64)
+    s.close()
+    return out
+
+
+def _batch_fields(b, k):
+    phi, u, _ = b.fields(k)
+    b.sync()
+    return phi.cpu().numpy().astype(np.float64), u.cpu().numpy().astype(np.float64)
+
+
+def test_batch_equals_single_domains():
+    from paper_2607_25444_amd import capi
+    ws = _domains()
+    b = capi.Batch(ws)
+    b.step(25)
+    for k, w in enumerate(ws):
+        phi_b, u_b = _batch_fields(b, k)
+        phi_s, u_s = _single(w, 25)
+        fl = w.solid == 0
+        # identical per-node arithmetic; only the FP64 volume sums run in another
+        # tile order, so lambda differs in its last bits and phi by an ulp here and there
+        assert np.abs(phi_b - phi_s)[fl].max() <= 2e-6
+        assert np.abs(u_b - u_s).max() <= 2e-5 * max(np.abs(u_s).max(), 1e-9) + 1e-12
+    b.close()
+
+
+def test_batch_against_oracle(orc):
+    from paper_2607_25444_amd import capi
+    ws = _domains()[:3]
+    b = capi.Batch(ws)
+    b.step(10)
+    for k, w in enumerate(ws):
+        phi_b, u_b = _batch_fields(b, k)
+        o = orc.OracleSim.create(w.shape, w.solid, w.theta.astype(np.float64), orc.Params(**w.params),
+                                 w.phi0.astype(np.float64))
+        o.step(10)
+        fl = w.solid == 0
+        assert np.abs(phi_b - o.phi)[fl].max() <= 5e-6
+        uo = o.u.reshape(3, -1)[:, fl]
+        assert np.abs(u_b.reshape(3, -1)[:, fl] - uo).max() <= 5e-5 * np.abs(uo).max()
+    vols = b.volumes()
+    for k, w in enumerate(ws):
+        M0 = float(w.phi0.astype(np.float64)[w.solid == 0].sum())
+        assert vols[k] == pytest.approx(M0, rel=1e-6)
+    b.close()
+
+
+@pytest.mark.parametrize("sched", [(0, 256, 0, 3, 2, 0, 1), (0, 512, 0, 5, 0, 1, 0), (16, 4, 4, 5, 0, 0, 0), (32, 8, 1, 3, 1, 1, 1), (64, 4, 1, 1, 4, 0, 1),
+                                   (16, 16, 1, 2, 2, 1, 0), (128, 2, 1, 6, 8, 0, 1), (32, 4, 2, 4, 1, 0, 1)])
+def test_schedules_agree(sched):
+    from paper_2607_25444_amd import capi
+    ws = _domains()
+    ref = capi.Batch(ws)
+    ref.step(12)
+    b = capi.Batch(ws)
+    b.set_schedule(*sched)
+    assert b.schedule() == sched
+    b.step(12)
+    for k in range(len(ws)):
+        p0, u0 = _batch_fields(ref, k)
+        p1, u1 = _batch_fields(b, k)
+        assert np.abs(p0 - p1).max() <= 2e-6
+        assert np.abs(u0 - u1).max() <= 2e-5 * max(np.abs(u0).max(), 1e-9) + 1e-12
+    ref.close()
+    b.close()
+
+
+def test_graph_replay_bitwise():
+    from paper_2607_25444_amd import capi
+    ws = _domains()
+    a = capi.Batch(ws).set_schedule(32, 4, 2, 3, 2, 0, 0)
+    c = capi.Batch(ws).set_schedule(32, 4, 2, 3, 2, 0, 1)
+    a.step(9)
+    c.step(9)
+    for k in range(len(ws)):
+        pa, ua = _batch_fields(a, k)
+        pc, uc = _batch_fields(c, k)
+        np.testing.assert_array_equal(pa, pc)
+        np.testing.assert_array_equal(ua, uc)
+
+
+def test_autotune_keeps_state_and_caches(tmp_path):
+    from paper_2607_25444_amd import capi
+    ws = _domains()
+    b = capi.Batch(ws)
+    b.step(3)
+    before = [_batch_fields(b, k) for k in range(len(ws))]
+    path = str(tmp_path / "tune.json")
+    ms = b.autotune(path, trial_steps=2)
+    assert ms > 0
+    after = [_batch_fields(b, k) for k in range(len(ws))]
+    for (p0, u0), (p1, u1) in zip(before, after):
+        np.testing.assert_array_equal(p0, p1)
+        np.testing.assert_array_equal(u0, u1)
+    chosen = b.schedule()
+    b.step(4)
+    b2 = capi.Batch(ws)
+    assert b2.autotune(path, trial_steps=2) == -1.0  # served from the cache
+    assert b2.schedule()[:6] == chosen[:6]
+    import json
+    d = json.load(open(path))
+    assert len(d["schedules"]) == 1
+    b.close()
+    b2.close()
