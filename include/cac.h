@@ -168,6 +168,55 @@ cac_status cac_profile_step(cac_handle *h, int nsteps, double *ms);
 cac_status cac_destroy(cac_handle *h);
 
 /* ------------------------------------------------------------------------
+ * Adjoint (reverse mode) of the step.  The paper defines no adjoint; this is
+ * the exact transpose of the Jacobian of the discrete step W -> H -> P -> V
+ * (Sec. II), used to differentiate a loss of the final phase field with
+ * respect to the per-wall-node contact angles (Sec. II B, Eqs. (43)-(46)) and
+ * the initial phase field.  At non-smooth points (minmod, upwind side, the
+ * band of Eq. (51), the normal guard, lambda_s of Eq. (47), |grad_par|, the
+ * regularised cotangent) the branch taken by the forward step is
+ * differentiated.  All reverse kernels are deterministic; dL/dtheta is
+ * accumulated over the steps in FP64.
+ * ------------------------------------------------------------------------ */
+
+/* Advance nsteps steps from the current state, exactly as cac_step, and record
+ * the sweep for cac_tape_backward: the state (populations, phi, previous
+ * ghosts) is copied every K steps (checkpoints, ceil(nsteps/K) x 29 N floats)
+ * together with the contact angles in use.  cac_set_state and
+ * cac_set_geometry discard the recording.  Asynchronous.
+ * Errors: CAC_ERR_ARG (nsteps or K < 1), CAC_ERR_STATE (no state),
+ * CAC_ERR_ALLOC. */
+cac_status cac_tape_forward(cac_handle *h, int nsteps, int K);
+
+/* Reverse sweep of the recorded sweep.  d_phibar (device, N floats): cotangent
+ * dL/dphi of the phase field after the last recorded step, on all nodes (wall
+ * nodes: the ghost values that cac_get_fields reports).  Outputs:
+ * d_dtheta (device, n_b doubles, wall-node order) = dL/dtheta in radians^-1
+ * (zero for skipped wall nodes); d_phibar0 (device, N floats, or NULL) =
+ * dL/dphi of the phase field passed to cac_set_state (fluid values and initial
+ * ghosts).  Each segment of K steps is replayed from its checkpoint into rings
+ * of about (33 K + 70) N floats (allocated on first use), then reversed step
+ * by step.  The live state is not changed.  Asynchronous.
+ * Errors: CAC_ERR_ARG (null pointer), CAC_ERR_STATE (nothing recorded, or the
+ * geometry changed since), CAC_ERR_ALLOC. */
+cac_status cac_tape_backward(cac_handle *h, const float *d_phibar, double *d_dtheta, float *d_phibar0);
+
+/* Loss L = 1/2 sum over fluid nodes of (phi - phi_target)^2 of the current
+ * state, accumulated in FP64.  d_seed (device, N floats, or NULL): receives
+ * dL/dphi = phi - phi_target on fluid nodes and 0 on solid nodes.  loss_host
+ * (or NULL): the loss; when given, the call synchronises.
+ * Errors: CAC_ERR_ARG, CAC_ERR_STATE (no state). */
+cac_status cac_loss(cac_handle *h, const float *d_phi_target, float *d_seed, double *loss_host);
+
+/* cac_tape_forward(nsteps, K), then cac_loss against d_phi_target (device, N
+ * floats), then the reverse sweep seeded with dL/dphi: loss_host (or NULL)
+ * receives L and d_dL_dtheta (device, n_b doubles) the gradient.  Leaves the
+ * state after step nsteps.  Synchronises; errors as the three calls, and
+ * CAC_ERR_NONFINITE from the watchdog. */
+cac_status cac_adjoint(cac_handle *h, int nsteps, int K, const float *d_phi_target, double *loss_host,
+                       double *d_dL_dtheta);
+
+/* ------------------------------------------------------------------------
  * Batched step: many independent lattices ("domains") of uneven size, contact
  * angle and parameters advanced together, one launch per substep, by
  * persistent workgroups that walk a list of (domain, tile) work items.  The

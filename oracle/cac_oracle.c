@@ -34,6 +34,7 @@
  *   u[d*N+n], pstar[n]  macroscopic fields of the last collision
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -624,6 +625,9 @@ int orc_volume(const orc_params *p, int nx, int ny, int nz, const uint8_t *solid
     if (lambda) *lambda = lam;
     return 0;
 }
+
+/* Threads the OpenMP loops use. */
+int orc_num_threads(void) { return omp_get_max_threads(); }
 
 /* Phase-field mass, Eq. (48): sum of phi over fluid nodes. */
 double orc_mass(int nx, int ny, int nz, const uint8_t *solid, const double *phi)

@@ -99,6 +99,7 @@ def lib():
         L.orc_init.argtypes = [C.c_int, C.c_int, C.c_int, u8p, dp, dp, dp, dp, dp, dp]
         L.orc_step.argtypes = [pp, C.c_int, C.c_int, C.c_int, u8p, dp, dp, dp, dp, dp, C.c_double, C.c_int, dp]
         L.orc_step.restype = C.c_int
+        L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -233,6 +234,10 @@ def volume(params, shape, solid, phistar, M_target):
     p = params.c_struct()
     lib().orc_volume(C.byref(p), nx, ny, nz, _u8(solid), _d(phistar), float(M_target), _d(out), C.byref(lam))
     return out, lam.value
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 def mass(shape, solid, phi):

@@ -60,6 +60,10 @@ SIGNATURES = {
     "cac_set_launch": (C.c_int, [_hp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
     "cac_profile_step": (C.c_int, [_hp, C.c_int, C.POINTER(C.c_double)]),
     "cac_destroy": (C.c_int, [_hp]),
+    "cac_tape_forward": (C.c_int, [_hp, C.c_int, C.c_int]),
+    "cac_tape_backward": (C.c_int, [_hp, _vp, _vp, _vp]),
+    "cac_loss": (C.c_int, [_hp, _vp, _vp, C.POINTER(C.c_double)]),
+    "cac_adjoint": (C.c_int, [_hp, C.c_int, C.c_int, _vp, C.POINTER(C.c_double), _vp]),
     "cac_batch_init": (C.c_int, [C.POINTER(_hp), C.c_int, C.POINTER(DomainDesc), ALLOC_FN, _vp, _vp]),
     "cac_batch_set_schedule": (C.c_int, [_hp] + [C.c_int] * 7),
     "cac_batch_get_schedule": (C.c_int, [_hp, C.POINTER(C.c_int)]),
@@ -266,6 +270,80 @@ class Sim:
         self._check(self.lib.cac_set_launch(self.h, int(bx), int(by), int(bz), int(phase_tile),
                                             int(bool(use_graph))))
         return self
+
+    # -------------------------------------------------------------- adjoint
+    def tape_forward(self, nsteps, K):
+        """Advance nsteps steps and record them (checkpoints every K) for tape_backward."""
+        self._check(self.lib.cac_tape_forward(self.h, int(nsteps), int(K)))
+        return self
+
+    def tape_backward(self, phibar, want_phi0=True):
+        """Reverse sweep seeded with dL/dphi after the recorded steps (device, N).
+        Returns (dL/dtheta per wall node as float64, dL/dphi0 as float32 or None)."""
+        tc = self.torch
+        pb = tc.as_tensor(phibar, dtype=tc.float32, device=self.device).contiguous().reshape(-1)
+        assert pb.numel() == self.N
+        dth = tc.zeros(max(self.nwall, 1), dtype=tc.float64, device=self.device)
+        dphi0 = tc.empty(self.N, dtype=tc.float32, device=self.device) if want_phi0 else None
+        self._check(self.lib.cac_tape_backward(self.h, _ptr(pb), _ptr(dth), _ptr(dphi0)))
+        self._keep_seed = pb
+        return dth[:self.nwall], dphi0
+
+    def loss(self, phi_target):
+        """(L, dL/dphi) for L = 1/2 sum_fluid (phi - phi_target)^2 of the current state."""
+        tc = self.torch
+        tgt = tc.as_tensor(phi_target, dtype=tc.float32, device=self.device).contiguous().reshape(-1)
+        seed = tc.empty(self.N, dtype=tc.float32, device=self.device)
+        out = C.c_double()
+        self._check(self.lib.cac_loss(self.h, _ptr(tgt), _ptr(seed), C.byref(out)))
+        return out.value, seed
+
+    def adjoint(self, nsteps, K, phi_target):
+        """Forward nsteps from the current state, loss against phi_target, reverse sweep:
+        returns (L, dL/dtheta per wall node, float64 device tensor)."""
+        tc = self.torch
+        tgt = tc.as_tensor(phi_target, dtype=tc.float32, device=self.device).contiguous().reshape(-1)
+        dth = tc.zeros(max(self.nwall, 1), dtype=tc.float64, device=self.device)
+        out = C.c_double()
+        self._check(self.lib.cac_adjoint(self.h, int(nsteps), int(K), _ptr(tgt), C.byref(out), _ptr(dth)))
+        return out.value, dth[:self.nwall]
+
+
+def _autograd_function():
+    import torch
+
+    class CACStep(torch.autograd.Function):
+        """phi^N = CACStep.apply(theta, phi0, sim, nsteps, K): nsteps coupled steps of `sim`
+        from the initial phase field phi0 (N) with contact angles theta (one per wall node).
+        The backward pass is the library's reverse sweep (checkpoints every K steps) and
+        returns dL/dtheta and dL/dphi0."""
+
+        @staticmethod
+        def forward(ctx, theta, phi0, sim, nsteps, K):
+            sim.set_contact_angles(theta.detach())
+            sim.set_state(phi0.detach())
+            sim.tape_forward(nsteps, K)
+            ctx.sim = sim
+            phi = sim.fields()[0]
+            return phi
+
+        @staticmethod
+        def backward(ctx, gphi):
+            dth, dphi0 = ctx.sim.tape_backward(gphi.detach(), want_phi0=True)
+            return dth.to(torch.float32), dphi0, None, None, None
+
+    return CACStep
+
+
+_CACStep = None
+
+
+def cac_step_function():
+    """The torch.autograd.Function wrapping a recorded rollout (built on first use)."""
+    global _CACStep
+    if _CACStep is None:
+        _CACStep = _autograd_function()
+    return _CACStep
 
 
 def from_workload(w, device=None) -> Sim:

@@ -1,0 +1,317 @@
+// adjoint_runtime.cpp -- host side of the adjoint (cac_tape_*, cac_loss,
+// cac_adjoint): a recorded forward sweep keeps the state every K steps
+// (checkpoints); the reverse sweep replays one segment at a time, keeping
+// every step of the segment in rings (populations entering the step, phi with
+// its ghosts, velocity, phi before the volume correction), then runs the
+// reverse steps of the segment backwards.  Device memory is bounded by
+// ceil(nsteps/K) checkpoints of 29 N words plus rings of about 33 K N words.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "adjoint_tables.hpp"
+#include "handle.hpp"
+
+namespace cac {
+
+struct AdjTape {
+    int nsteps = 0, K = 0;
+    bool recorded = false;       // cleared by cac_set_state (the target mass may change)
+    long long rec_serial = -1;   // geometry of the recorded sweep
+    float *theta = nullptr;      // contact angles of the recorded sweep (nwall)
+    int theta_cap = 0;
+    std::vector<float *> ck;     // checkpoints: 27N populations, N phi (current), N phi (previous ghosts)
+    int ring_K = 0;              // rings sized for this K
+    std::vector<float *> rf;     // K+1 population sets: rf[j] enters step j of the segment
+    std::vector<float *> rphi;   // K+2 phase fields: rphi[j+1] = phi with the ghosts of step j
+    std::vector<float *> ru;     // K velocities (zero on solid nodes)
+    std::vector<float *> rps;    // K fields phi* (before the correction)
+    // reverse state
+    bool adj_ready = false;
+    float *mb[2] = {nullptr, nullptr}, *pb[2] = {nullptr, nullptr};
+    float *rec = nullptr, *awb = nullptr, *seed = nullptr;
+    double *thb = nullptr, *red = nullptr, *rs = nullptr;
+    // donor tables (rebuilt when the geometry changes)
+    long long geom_serial = -1;
+    float4 *dg = nullptr;
+    int32_t *don_node = nullptr, *don_start = nullptr, *don_wall = nullptr, *don_map = nullptr;
+    uint32_t *near = nullptr;
+    int ndon = 0;
+    uint32_t nnear = 0;
+};
+
+void tape_free(cac_handle *h)
+{
+    delete h->tape;  // device memory belongs to the handle's allocations
+    h->tape = nullptr;
+}
+
+void tape_invalidate(cac_handle *h)
+{
+    if (h->tape) h->tape->recorded = false;
+}
+
+namespace {
+
+AdjTape *tape_of(cac_handle *h)
+{
+    if (!h->tape) h->tape = new AdjTape();
+    return h->tape;
+}
+
+template <class T>
+bool alloc_n(cac_handle *h, T *&p, size_t n)
+{
+    p = (T *)dev_alloc(h, std::max<size_t>(n, 1) * sizeof(T));
+    return p != nullptr;
+}
+
+cac_status ensure_rings(cac_handle *h, AdjTape &T)
+{
+    const size_t N = h->g.N;
+    const int K = T.K;
+    while ((int)T.rf.size() < K + 1) {
+        float *p;
+        if (!alloc_n(h, p, 27 * N)) return fail(h, CAC_ERR_ALLOC, "adjoint ring");
+        T.rf.push_back(p);
+    }
+    while ((int)T.rphi.size() < K + 2) {
+        float *p;
+        if (!alloc_n(h, p, N)) return fail(h, CAC_ERR_ALLOC, "adjoint ring");
+        T.rphi.push_back(p);
+    }
+    while ((int)T.ru.size() < K) {
+        float *p;
+        if (!alloc_n(h, p, 3 * N)) return fail(h, CAC_ERR_ALLOC, "adjoint ring");
+        // the collision never writes solid nodes: keep their velocity at zero
+        HIPCHK(h, hipMemsetAsync(p, 0, 3 * N * sizeof(float), h->stream));
+        T.ru.push_back(p);
+    }
+    while ((int)T.rps.size() < K) {
+        float *p;
+        if (!alloc_n(h, p, N)) return fail(h, CAC_ERR_ALLOC, "adjoint ring");
+        T.rps.push_back(p);
+    }
+    if (!T.adj_ready) {
+        bool ok = alloc_n(h, T.mb[0], 10 * N) && alloc_n(h, T.mb[1], 10 * N) && alloc_n(h, T.pb[0], N) &&
+                  alloc_n(h, T.pb[1], N) && alloc_n(h, T.rec, 5 * N) && alloc_n(h, T.awb, 3 * N) &&
+                  (T.seed || alloc_n(h, T.seed, N)) &&
+                  (T.red || alloc_n(h, T.red, 3 * (size_t)adj_red_blocks(h->g) + 64)) && (T.rs || alloc_n(h, T.rs, 8));
+        if (!ok) return fail(h, CAC_ERR_ALLOC, "adjoint buffers");
+        HIPCHK(h, hipMemsetAsync(T.awb, 0, 3 * N * sizeof(float), h->stream));
+        T.adj_ready = true;
+    }
+    return CAC_OK;
+}
+
+cac_status ensure_tables(cac_handle *h, AdjTape &T)
+{
+    if (T.geom_serial == h->geom_serial) return CAC_OK;
+    DonorTables D;
+    build_donor_tables(h->g, h->widx.data(), h->wdonor.data(), (int)h->widx.size(), D);
+    T.ndon = (int)D.don_node.size();
+    T.nnear = (uint32_t)D.near.size();
+    const size_t N = h->g.N;
+    bool ok = alloc_n(h, T.dg, T.ndon) && alloc_n(h, T.don_node, T.ndon) && alloc_n(h, T.don_start, T.ndon + 1) &&
+              alloc_n(h, T.don_wall, D.don_wall.size()) && alloc_n(h, T.don_map, N) && alloc_n(h, T.near, T.nnear) &&
+              alloc_n(h, T.thb, h->widx.size());
+    if (!ok) return fail(h, CAC_ERR_ALLOC, "adjoint donor tables");
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+        return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream) : hipSuccess;
+    };
+    HIPCHK(h, up(T.don_node, D.don_node.data(), D.don_node.size() * 4));
+    HIPCHK(h, up(T.don_start, D.don_start.data(), D.don_start.size() * 4));
+    HIPCHK(h, up(T.don_wall, D.don_wall.data(), D.don_wall.size() * 4));
+    HIPCHK(h, up(T.don_map, D.don_map.data(), D.don_map.size() * 4));
+    HIPCHK(h, up(T.near, D.near.data(), D.near.size() * 4));
+    HIPCHK(h, hipStreamSynchronize(h->stream));  // host vectors go out of scope
+    T.geom_serial = h->geom_serial;
+    return CAC_OK;
+}
+
+// Forward step j of the current segment, keeping its state in the rings.
+cac_status replay_step(cac_handle *h, AdjTape &T, int j)
+{
+    Fields F = h->F;
+    F.theta = T.theta;
+    F.phi[0] = T.rphi[j + 1];
+    F.phi[1] = T.rphi[j];
+    HIPCHK(h, launch_ghost(h->g, h->dp, F, 0, h->stream));
+    F.f[0] = T.rf[j];
+    F.f[1] = T.rf[j + 1];
+    F.u = T.ru[j];
+    HIPCHK(h, launch_hydro(h->g, h->t, h->dp, F, 0, 0, h->stream));
+    F.phi[1] = T.rps[j];
+    HIPCHK(h, launch_phase(h->g, h->t, h->dp, F, 0, h->stream));
+    HIPCHK(h, launch_volume_copy(h->g, h->t, h->dp, F, T.rps[j], T.rphi[j + 1], T.rphi[j + 2], h->stream));
+    return CAC_OK;
+}
+
+// Reverse of step j of the current segment; cotangents move from parity c to c ^ 1.
+cac_status reverse_step(cac_handle *h, AdjTape &T, int j, int c)
+{
+    AdjStep S{};
+    S.fprev = T.rf[j];
+    S.phihat = T.rphi[j + 1];
+    S.phiold = T.rphi[j];
+    S.u = T.ru[j];
+    S.phistar = T.rps[j];
+    S.pb_in = T.pb[c];
+    S.mb_in = T.mb[c];
+    S.pb_out = T.pb[c ^ 1];
+    S.mb_out = T.mb[c ^ 1];
+    S.rec = T.rec;
+    S.awb = T.awb;
+    S.nbr = h->F.nbr;
+    S.solid = h->F.solid;
+    S.widx = h->F.wall_idx;
+    S.wq = h->F.wall_q;
+    S.wn = h->F.wall_n;
+    S.theta = T.theta;
+    S.don_start = T.don_start;
+    S.don_wall = T.don_wall;
+    S.don_node = T.don_node;
+    S.ndon = T.ndon;
+    S.don_map = T.don_map;
+    S.dg = T.dg;
+    S.near = T.near;
+    S.nnear = T.nnear;
+    S.thb = T.thb;
+    S.red = T.red;
+    S.rs = T.rs;
+    S.scal = h->F.scal;
+    HIPCHK(h, launch_adj_vsum(h->g, h->dp, S, h->stream));
+    HIPCHK(h, launch_adj_main(h->g, h->t, h->dp, S, h->stream));
+    HIPCHK(h, launch_adj_assemble(h->g, h->t, S, h->stream));
+    HIPCHK(h, launch_adj_wall(h->g, h->dp, S, h->stream));
+    HIPCHK(h, launch_adj_fix(h->g, S, h->stream));
+    return CAC_OK;
+}
+
+}  // namespace
+}  // namespace cac
+
+using namespace cac;
+
+extern "C" {
+
+cac_status cac_tape_forward(cac_handle *h, int nsteps, int K)
+{
+    if (!h) return CAC_ERR_ARG;
+    if (nsteps < 1 || K < 1) return fail(h, CAC_ERR_ARG, "nsteps and K must be >= 1");
+    if (!h->state) return fail(h, CAC_ERR_STATE, "cac_set_state must come first");
+    AdjTape &T = *tape_of(h);
+    T.recorded = false;
+    const size_t N = h->g.N;
+    const int nck = (nsteps + K - 1) / K;
+    while ((int)T.ck.size() < nck) {
+        float *p;
+        if (!alloc_n(h, p, 29 * N)) return fail(h, CAC_ERR_ALLOC, "checkpoint storage");
+        T.ck.push_back(p);
+    }
+    const int nwall = h->F.nwall;
+    if (nwall > T.theta_cap) {
+        if (!alloc_n(h, T.theta, (size_t)nwall + 64)) return fail(h, CAC_ERR_ALLOC, "tape angles");
+        T.theta_cap = nwall + 64;
+    }
+    if (nwall)
+        HIPCHK(h, hipMemcpyAsync(T.theta, h->F.theta, nwall * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    for (int n = 0; n < nsteps; ++n) {
+        if (n % K == 0) {
+            float *c = T.ck[n / K];
+            const int cur = h->cur;
+            HIPCHK(h, hipMemcpyAsync(c, h->F.f[cur], 27 * N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+            HIPCHK(h, hipMemcpyAsync(c + 27 * N, h->F.phi[cur], N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+            HIPCHK(h, hipMemcpyAsync(c + 28 * N, h->F.phi[cur ^ 1], N * sizeof(float), hipMemcpyDeviceToDevice,
+                                     h->stream));
+        }
+        cac_status st = cac_step(h, 1);
+        if (st != CAC_OK) return st;
+    }
+    T.nsteps = nsteps;
+    T.K = K;
+    T.rec_serial = h->geom_serial;
+    T.recorded = true;
+    return CAC_OK;
+}
+
+cac_status cac_tape_backward(cac_handle *h, const float *d_phibar, double *d_dtheta, float *d_phibar0)
+{
+    if (!h || !d_phibar || !d_dtheta) return CAC_ERR_ARG;
+    AdjTape *Tp = h->tape;
+    if (!Tp || !Tp->recorded) return fail(h, CAC_ERR_STATE, "no recorded sweep (cac_tape_forward)");
+    if (Tp->rec_serial != h->geom_serial) return fail(h, CAC_ERR_STATE, "geometry changed after the recorded sweep");
+    AdjTape &T = *Tp;
+    cac_status st = ensure_rings(h, T);
+    if (st != CAC_OK) return st;
+    st = ensure_tables(h, T);
+    if (st != CAC_OK) return st;
+    const size_t N = h->g.N;
+    const int nwall = h->F.nwall;
+    HIPCHK(h, hipMemcpyAsync(T.pb[0], d_phibar, N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemsetAsync(T.mb[0], 0, 10 * N * sizeof(float), h->stream));
+    if (nwall) HIPCHK(h, hipMemsetAsync(T.thb, 0, nwall * sizeof(double), h->stream));
+    HIPCHK(h, hipMemsetAsync(T.rs, 0, 4 * sizeof(double), h->stream));
+    int c = 0;
+    const int nck = (T.nsteps + T.K - 1) / T.K;
+    for (int seg = nck - 1; seg >= 0; --seg) {
+        const int n0 = seg * T.K;
+        const int L = std::min(T.K, T.nsteps - n0);
+        const float *ck = T.ck[seg];
+        HIPCHK(h, hipMemcpyAsync(T.rf[0], ck, 27 * N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(T.rphi[1], ck + 27 * N, N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(T.rphi[0], ck + 28 * N, N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+        for (int j = 0; j < L; ++j) {
+            st = replay_step(h, T, j);
+            if (st != CAC_OK) return st;
+        }
+        for (int j = L - 1; j >= 0; --j) {
+            st = reverse_step(h, T, j, c);
+            if (st != CAC_OK) return st;
+            c ^= 1;
+        }
+    }
+    if (nwall)
+        HIPCHK(h, hipMemcpyAsync(d_dtheta, T.thb, nwall * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    if (d_phibar0) {
+        HIPCHK(h, launch_adj_mtarget(h->g, h->F.solid, T.pb[c], T.rs, h->stream));
+        HIPCHK(h, hipMemcpyAsync(d_phibar0, T.pb[c], N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    }
+    return CAC_OK;
+}
+
+cac_status cac_loss(cac_handle *h, const float *d_phi_target, float *d_seed, double *loss_host)
+{
+    if (!h || !d_phi_target) return CAC_ERR_ARG;
+    if (!h->state) return fail(h, CAC_ERR_STATE, "no state");
+    AdjTape &T = *tape_of(h);
+    const size_t N = h->g.N;
+    if (!T.seed && !alloc_n(h, T.seed, N)) return fail(h, CAC_ERR_ALLOC, "seed");
+    if (!T.red && !alloc_n(h, T.red, 3 * (size_t)adj_red_blocks(h->g) + 64)) return fail(h, CAC_ERR_ALLOC, "partials");
+    if (!T.rs && !alloc_n(h, T.rs, 8)) return fail(h, CAC_ERR_ALLOC, "scalars");
+    HIPCHK(h, launch_loss_seed(h->g, h->F.solid, h->F.phi[h->cur], d_phi_target, d_seed ? d_seed : T.seed, T.red,
+                               T.rs + 4, h->stream));
+    if (loss_host) {
+        HIPCHK(h, hipMemcpyAsync(loss_host, T.rs + 4, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        return cac_sync(h);
+    }
+    return CAC_OK;
+}
+
+cac_status cac_adjoint(cac_handle *h, int nsteps, int K, const float *d_phi_target, double *loss_host,
+                       double *d_dL_dtheta)
+{
+    if (!h || !d_phi_target || !d_dL_dtheta) return CAC_ERR_ARG;
+    cac_status st = cac_tape_forward(h, nsteps, K);
+    if (st != CAC_OK) return st;
+    AdjTape &T = *h->tape;
+    st = cac_loss(h, d_phi_target, nullptr, nullptr);
+    if (st != CAC_OK) return st;
+    st = cac_tape_backward(h, T.seed, d_dL_dtheta, nullptr);
+    if (st != CAC_OK) return st;
+    if (loss_host) HIPCHK(h, hipMemcpyAsync(loss_host, T.rs + 4, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    return cac_sync(h);
+}
+
+}  // extern "C"

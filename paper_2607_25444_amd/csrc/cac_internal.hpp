@@ -158,4 +158,56 @@ hipError_t launch_mass(const Grid &g, const Tiling &t, const Fields &F, const fl
 hipError_t launch_gather(const Grid &g, const Fields &F, int fcur, int pcur, int stepped, float *phi_out,
                          float *pstar_out, hipStream_t s);
 
+// ---------------------------------------------------------------- adjoint
+// One reverse step (the transpose of the Jacobian of W -> H -> P -> V at the
+// recorded forward state).  Cotangents of the populations are kept as the
+// cotangents of the ten moments the collision reads (p*, j, P = sum f c c):
+// the collision depends on f only through them, so the cotangent of the
+// pulled population f_i(x) is  mb0 + c_i.(mb1..3) + c_i c_i : (mb4..9).
+struct AdjStep {
+    // recorded forward state of the step
+    const float *fprev;    // post-collision populations entering the step (pull layout)
+    const float *phihat;   // phi^n on fluid nodes with this step's ghosts on wall nodes
+    const float *phiold;   // previous ghosts (read on wall nodes)
+    const float *u;        // velocity of the step (zero on solid nodes)
+    const float *phistar;  // phase field before the volume correction (fluid nodes)
+    // cotangents
+    const float *pb_in;    // of phi^{n+1} (all nodes)
+    const float *mb_in;    // 10 planes: of the moments of step n+1
+    float *pb_out;         // of phi-hat, then (after the wall pass) of phi^n
+    float *mb_out;         // 10 planes: of the moments of step n
+    float *rec;            // 5 planes: stencil cotangents (grad x,y,z; Laplacian; local)
+    float *awb;            // 3 planes: of the compressive flux on wall nodes
+    // geometry
+    const uint32_t *nbr;
+    const uint8_t *solid;
+    const int32_t *widx;
+    const uint8_t *wq;
+    const float *wn, *theta;
+    const int32_t *don_start, *don_wall, *don_node;  // donors with their wall nodes (CSR)
+    int ndon;
+    const int32_t *don_map;  // node -> donor slot or -1
+    float4 *dg;              // per donor: (cotangent of phi_f, of grad phi at the donor)
+    const uint32_t *near;    // nodes within one link of a donor; bit 31: active wall node
+    uint32_t nnear;
+    double *thb;             // dL/dtheta per wall node (accumulated)
+    double *red;             // reduction partials
+    double *rs;              // [0] lambda, [1] cotangent mean of the correction, [3] dL/dM_target, [4] loss
+    const double *scal;      // forward scalars ([0] M_target)
+};
+
+hipError_t launch_volume_copy(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F,
+                              const float *phistar, const float *phihat, float *out, hipStream_t s);
+uint32_t adj_red_blocks(const Grid &g);  // partial entries (3 doubles each) of the reductions
+hipError_t launch_adj_vsum(const Grid &g, const DevParams &p, const AdjStep &S, hipStream_t s);
+hipError_t launch_adj_main(const Grid &g, const Tiling &t, const DevParams &p, const AdjStep &S, hipStream_t s);
+hipError_t launch_adj_assemble(const Grid &g, const Tiling &t, const AdjStep &S, hipStream_t s);
+hipError_t launch_adj_wall(const Grid &g, const DevParams &p, const AdjStep &S, hipStream_t s);
+hipError_t launch_adj_fix(const Grid &g, const AdjStep &S, hipStream_t s);
+// pb += rs[3] on fluid nodes (the path of dL/dphi0 through the target volume)
+hipError_t launch_adj_mtarget(const Grid &g, const uint8_t *solid, float *pb, const double *rs, hipStream_t s);
+// seed = phi - target on fluid nodes (0 elsewhere) and out[0] = 1/2 sum_fluid (phi - target)^2 in FP64
+hipError_t launch_loss_seed(const Grid &g, const uint8_t *solid, const float *phi, const float *target, float *seed,
+                            double *red, double *out, hipStream_t s);
+
 }  // namespace cac

@@ -85,6 +85,25 @@ __global__ __launch_bounds__(256) void k_vol_apply(uint32_t N, const uint8_t *__
     if (v > eps_phi && v < 1.0f - eps_phi) phi[n] = (float)((double)v + lam * ((double)v * (1.0 - (double)v)));
 }
 
+// Out-of-place correction used when the forward sweep is recorded: phi* stays
+// intact for the reverse pass.  Solid nodes copy phi-hat (ghosts and skipped
+// walls keep their values, as in the in-place update).
+__global__ __launch_bounds__(256) void k_vol_copy(uint32_t N, const uint8_t *__restrict__ solid,
+                                                  const float *__restrict__ phistar, const float *__restrict__ phihat,
+                                                  float *__restrict__ out, const double *__restrict__ scal,
+                                                  float eps_phi)
+{
+    const uint32_t n = blockIdx.x * 256u + threadIdx.x;
+    if (n >= N) return;
+    if (solid[n]) {
+        out[n] = phihat[n];
+        return;
+    }
+    const double lam = scal[1];
+    const float v = phistar[n];
+    out[n] = (v > eps_phi && v < 1.0f - eps_phi) ? (float)((double)v + lam * ((double)v * (1.0 - (double)v))) : v;
+}
+
 // ------------------------------------------------------------------ init, mass, gather
 
 // Populations that stream into f^eq(p*0, u0): f*_j(y) = f^eq_j(x) at x = y + c_j
@@ -278,6 +297,16 @@ hipError_t launch_volume(const Grid &g, const Tiling &t, const DevParams &p, con
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_vol_apply<<<blocks_for(g.N, 256), 256, 0, s>>>(g.N, F.solid, F.phi[pnext], F.scal, p.eps_phi);
+    return hipGetLastError();
+}
+
+hipError_t launch_volume_copy(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F,
+                              const float *phistar, const float *phihat, float *out, hipStream_t s)
+{
+    k_vol_finalize<<<1, 1024, 0, s>>>(F.partial, phase_tiles(g, t), F.scal, p.volume_correction);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_vol_copy<<<blocks_for(g.N, 256), 256, 0, s>>>(g.N, F.solid, phistar, phihat, out, F.scal, p.eps_phi);
     return hipGetLastError();
 }
 

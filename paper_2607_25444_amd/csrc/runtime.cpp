@@ -11,35 +11,9 @@
 #include <vector>
 
 #include "../../include/cac.h"
-#include "cac_internal.hpp"
+#include "handle.hpp"
 
 using namespace cac;
-
-struct cac_handle {
-    int dev = 0;
-    Grid g{};
-    Tiling t{};
-    cac_params prm{};
-    DevParams dp{};
-    Fields F{};
-    hipStream_t stream = nullptr;
-    cac_alloc_fn alloc = nullptr;
-    void *alloc_user = nullptr;
-    std::vector<void *> owned;  // hipMalloc'd when no callback
-    bool geometry = false, state = false;
-    int cur = 0;                // parity of the A/B buffers holding the current state
-    long long steps = 0;
-    size_t partial_cap = 0;     // entries of F.partial
-    int wall_cap = 0;
-    // host copies of the wall tables
-    std::vector<int32_t> widx, wn6, wdonor;
-    int nskip = 0;
-    // graph replay of two steps (even/odd buffer parity)
-    bool use_graph = false;
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    hipStream_t cap_stream = nullptr;  // capture needs a stream other than the null stream
-    std::string err;
-};
 
 namespace cac {
 DevParams make_dev_params(const cac_params &p);
@@ -49,7 +23,7 @@ void build_geometry(const Grid &g, const uint8_t *solid, std::vector<uint32_t> &
 bool valid_params(const cac_params &p);
 }  // namespace cac
 
-namespace {
+namespace cac {
 
 cac_status fail(cac_handle *h, cac_status s, const char *fmt, ...)
 {
@@ -64,12 +38,6 @@ cac_status fail(cac_handle *h, cac_status s, const char *fmt, ...)
     return s;
 }
 
-#define HIPCHK(h, call)                                                                         \
-    do {                                                                                        \
-        hipError_t e_ = (call);                                                                 \
-        if (e_ != hipSuccess) return fail(h, CAC_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
-    } while (0)
-
 void *dev_alloc(cac_handle *h, size_t bytes)
 {
     bytes = (bytes + 255) & ~(size_t)255;
@@ -81,7 +49,7 @@ void *dev_alloc(cac_handle *h, size_t bytes)
     return p;
 }
 
-}  // namespace
+}  // namespace cac
 
 namespace cac {
 
@@ -210,7 +178,7 @@ void build_geometry(const Grid &g, const uint8_t *solid, std::vector<uint32_t> &
 
 }  // namespace cac
 
-namespace {
+namespace cac {
 
 cac_status run_step(cac_handle *h)
 {
@@ -223,6 +191,10 @@ cac_status run_step(cac_handle *h)
     h->steps++;
     return CAC_OK;
 }
+
+}  // namespace cac
+
+namespace {
 
 void drop_graphs(cac_handle *h)
 {
@@ -409,6 +381,8 @@ cac_status cac_set_geometry(cac_handle *h, const uint8_t *solid, const float *th
     HIPCHK(h, hipStreamSynchronize(h->stream));  // host vectors go out of scope
     h->geometry = true;
     h->state = false;
+    h->geom_serial++;
+    tape_invalidate(h);
     drop_graphs(h);
     if (h->nskip) fail(h, CAC_OK, "%d wall node(s) with a vanishing normal are skipped", h->nskip);
     return CAC_OK;
@@ -493,6 +467,7 @@ cac_status cac_set_state(cac_handle *h, const float *d_phi, const float *d_u, co
     h->cur = 0;
     h->steps = 0;
     h->state = true;
+    tape_invalidate(h);
     return CAC_OK;
 }
 
@@ -612,6 +587,7 @@ cac_status cac_destroy(cac_handle *h)
     if (!h) return CAC_ERR_ARG;
     (void)hipStreamSynchronize(h->stream);
     drop_graphs(h);
+    tape_free(h);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     for (void *q : h->owned) (void)hipFree(q);
     delete h;

@@ -48,7 +48,7 @@ struct Offs {
     uint32_t x[3], y[3], z[3];
 };
 
-__device__ __forceinline__ Offs node_offsets(const Grid &g, int x, int y, int z)
+__host__ __device__ __forceinline__ Offs node_offsets(const Grid &g, int x, int y, int z)
 {
     Offs o;
     o.x[0] = (uint32_t)(x ? x - 1 : g.nx - 1);
@@ -64,7 +64,7 @@ __device__ __forceinline__ Offs node_offsets(const Grid &g, int x, int y, int z)
 }
 
 template <int DX, int DY, int DZ>
-__device__ __forceinline__ uint32_t at(const Offs &o)
+__host__ __device__ __forceinline__ uint32_t at(const Offs &o)
 {
     return o.x[DX + 1] + o.y[DY + 1] + o.z[DZ + 1];
 }
@@ -79,7 +79,7 @@ __host__ __device__ constexpr float tw(int d) { return d == 0 ? 4.0f : 1.0f; }
 // Laplacian does not lose digits to cancellation):
 //   grad_x = sum_{dy,dz} t(dy) t(dz) [d(+1,dy,dz) - d(-1,dy,dz)] / 72
 //   lap    = sum t(dx) t(dy) t(dz) d / 36
-__device__ __forceinline__ void stencil_grad_lap(const float (&s)[27], float &gx, float &gy, float &gz, float &lap)
+__host__ __device__ __forceinline__ void stencil_grad_lap(const float (&s)[27], float &gx, float &gy, float &gz, float &lap)
 {
     const float c0 = s[13];
     float S[9];  // x-smoothed differences at (dy, dz)
@@ -415,7 +415,7 @@ __device__ __forceinline__ void block_sum2(double &x, double &y)
 // the value the ghost update assigned (zero unless wall_compression is on).
 // Each thread also accumulates sum(phi*) and sum(chi) (Eqs. (49), (51)) in
 // FP64; the workgroup writes one partial per tile.
-__device__ __forceinline__ int wrapc(int v, int n)
+__host__ __device__ __forceinline__ int wrapc(int v, int n)
 {
     v %= n;
     return v < 0 ? v + n : v;
@@ -448,7 +448,7 @@ __device__ __forceinline__ PlaneSums plane_sums(const float (&v)[9])
 
 // minmod of Eq. (32) in branch-free form: equal to 0 when ab <= 0, else the
 // argument of smaller magnitude.
-__device__ __forceinline__ float minmod2(float a, float b)
+__host__ __device__ __forceinline__ float minmod2(float a, float b)
 {
     return fmaxf(fminf(a, b), 0.0f) + fminf(fmaxf(a, b), 0.0f);
 }
