@@ -147,6 +147,73 @@ def bench_batch(torch, capi, W, steps, warmup, seed, singles=True, tune_cache=No
     return out
 
 
+def bench_adjoint(torch, capi, tuning, W, steps, K, seed):
+    """Reverse-mode sweep on the contact-angle inversion workload (128 x 128 x 64,
+    bump angle field): cac_tape_forward (steps, checkpoints every K) + loss +
+    cac_tape_backward, timed with HIP events on the library's stream, beside
+    the plain step on the same lattice."""
+    w = W.adjoint_128(seed)
+    nx, ny, nz = w.shape
+    launch = tuning.launch_for(w.shape)
+    target = W.tanh_droplet(w.shape, ((nx - 1) / 2 + 0.6, (ny - 1) / 2 - 0.4, 0.5), 25.0, 4.0).astype("float32")
+    sim = capi.Sim(w.shape, w.params)
+    sim.set_launch(*launch)
+    sim.set_geometry(w.solid, w.theta)
+    stream = sim.stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    # plain step on the same lattice
+    sim.set_state(w.phi0)
+    sim.step(20)
+    sim.sync()
+    ev[0].record(stream)
+    sim.step(steps)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    plain_ms = ev[0].elapsed_time(ev[1])
+    # warm-up sweep (allocates checkpoints and rings)
+    mem_before = torch.cuda.memory_allocated()
+    sim.set_state(w.phi0)
+    sim.tape_forward(steps, K)
+    _, seed_t = sim.loss(target)
+    sim.tape_backward(seed_t, want_phi0=False)
+    sim.sync()
+    mem0 = torch.cuda.memory_allocated()
+    # timed sweep
+    sim.set_state(w.phi0)
+    sim.sync()
+    ev[0].record(stream)
+    sim.tape_forward(steps, K)
+    ev[1].record(stream)
+    L, seed_t = sim.loss(target)
+    ev[2].record(stream)
+    dth, _ = sim.tape_backward(seed_t, want_phi0=False)
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    sim.sync()
+    fwd_ms = ev[0].elapsed_time(ev[1])
+    bwd_ms = ev[2].elapsed_time(ev[3])
+    tot_ms = ev[0].elapsed_time(ev[3])
+    n = w.n_fluid * steps
+    out = {
+        "workload": w.name,
+        "steps": steps,
+        "K": K,
+        "launch": list(launch),
+        "value": round(n / (tot_ms * 1e-3) / 1e6, 2),
+        "unit": "MLUPS (forward record + reverse sweep, per step of the rollout)",
+        "ms_per_step": round(tot_ms / steps, 5),
+        "ms_per_step_forward_record": round(fwd_ms / steps, 5),
+        "ms_per_step_reverse": round(bwd_ms / steps, 5),
+        "plain_mlups_same_lattice": round(n / (plain_ms * 1e-3) / 1e6, 2),
+        "ratio_to_plain": round(plain_ms / tot_ms, 4),
+        "loss": L,
+        "max_abs_dL_dtheta": float(dth.abs().max().item()),
+        "tape_bytes": int(mem0 - mem_before),
+    }
+    sim.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +226,9 @@ def main():
     ap.add_argument("--launch", default=None, help="bx,by,bz,graph,phase_tile")
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=1000)
+    ap.add_argument("--adjoint-K", type=int, default=50)
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 1 GiB device copy (HBM ceiling; counter calibration)")
     args = ap.parse_args()
@@ -272,6 +342,10 @@ def main():
         rec["batched"] = bench_batch(torch, capi, W, args.batch_steps, 10, args.seed)
         rec["batched"]["ratio_to_plain"] = round(rec["batched"]["value"] / rec["value"], 4)
         log(f"[bench] batched {rec['batched']}")
+    if not args.no_adjoint:
+        log("[bench] adjoint workload ...")
+        rec["adjoint"] = bench_adjoint(torch, capi, tuning, W, args.adjoint_steps, args.adjoint_K, args.seed)
+        log(f"[bench] adjoint {rec['adjoint']}")
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host ...")
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)

@@ -1,12 +1,13 @@
 // adjoint.hip -- gfx950 kernels of the reverse (adjoint) step.
 //
 // One reverse step at the recorded forward state of step n:
-//   k_adj_vsum / k_adj_vfin  FP64 sums sum(pb chi), sum(phi*), sum(chi) of the
+//   k_adj_vsum, k_adj_vfin   FP64 sums sum(pb chi), sum(phi*), sum(chi) of the
 //                            volume correction's transpose -> lambda, cbar
+//   k_adj_psi                psi = cotangent of phi* (fluid nodes)
 //   k_adj_main               per node: transposes of V, P and the collision;
 //                            the transpose of the pull streaming is a gather
 //                            of the neighbours' moment cotangents
-//   k_adj_assemble           transpose of the gradient / Laplacian stencils
+//   k_adj_assemble_lds       transpose of the gradient / Laplacian stencils (2.5-D LDS)
 //   k_adj_wall               transpose of the ghost update per donor node,
 //                            dL/dtheta accumulated in FP64 per wall node
 //   k_adj_fix                donor-stencil transpose on the nodes next to donors
@@ -50,19 +51,26 @@ __device__ __forceinline__ void block_sum3(double &x, double &y, double &z)
 
 static inline unsigned nblocks(uint32_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
 
-// Per-block sums over fluid nodes of pb chi(phi*), phi*, chi(phi*) (Eqs. (49), (51)).
+// Per-block FP64 sums over fluid nodes of pb chi(phi*), phi*, chi(phi*)
+// (Eqs. (49), (51)); each thread covers ADJ_VSUM_PER_THREAD nodes.
+constexpr uint32_t ADJ_VSUM_PER_THREAD = 8;
+
 __global__ __launch_bounds__(256) void k_adj_vsum(uint32_t N, const uint8_t *__restrict__ solid,
                                                   const float *__restrict__ pb, const float *__restrict__ phistar,
                                                   float eps, double *__restrict__ red)
 {
-    const uint32_t n = blockIdx.x * 256u + threadIdx.x;
     double a = 0.0, b = 0.0, c = 0.0;
-    if (n < N && !solid[n]) {
-        const float v = phistar[n];
-        b = (double)v;
-        if (v > eps && v < 1.0f - eps) {
-            c = (double)v * (1.0 - (double)v);
-            a = (double)pb[n] * c;
+#pragma unroll
+    for (uint32_t r = 0; r < ADJ_VSUM_PER_THREAD; ++r) {
+        const uint32_t n = (blockIdx.x * ADJ_VSUM_PER_THREAD + r) * 256u + threadIdx.x;
+        if (n < N && !solid[n]) {
+            const float v = phistar[n];
+            b += (double)v;
+            if (v > eps && v < 1.0f - eps) {
+                const double ch = (double)v * (1.0 - (double)v);
+                c += ch;
+                a += (double)pb[n] * ch;
+            }
         }
     }
     block_sum3<256>(a, b, c);
@@ -74,7 +82,7 @@ __global__ __launch_bounds__(256) void k_adj_vsum(uint32_t N, const uint8_t *__r
 }
 
 // lambda = (M_target - sum phi*) / W and cbar = sum(pb chi) / W, zero when W = 0
-// or the correction is off.
+// or the correction is off; partials added in a fixed order.
 __global__ __launch_bounds__(1024) void k_adj_vfin(const double *__restrict__ red, uint32_t np,
                                                    const double *__restrict__ scal, double *__restrict__ rs, int vc)
 {
@@ -93,6 +101,12 @@ __global__ __launch_bounds__(1024) void k_adj_vfin(const double *__restrict__ re
     }
 }
 
+__global__ __launch_bounds__(256) void k_adj_psi(uint32_t N, DevParams p, AdjStep S)
+{
+    const uint32_t n = blockIdx.x * 256u + threadIdx.x;
+    if (n < N) adj_psi_node(p, S, n);
+}
+
 // Add the target-volume path to dL/dphi0: M_target is the fluid sum of phi0.
 __global__ __launch_bounds__(256) void k_add_fluid(uint32_t N, const uint8_t *__restrict__ solid,
                                                    float *__restrict__ pb, const double *__restrict__ rs)
@@ -108,11 +122,77 @@ __global__ __launch_bounds__(NT) void k_adj_main(Grid g, Tiling t, DevParams p, 
     if (nd.in) adj_main_node(g, p, S, nd.x, nd.y, nd.z);
 }
 
-template <int NT>
-__global__ __launch_bounds__(NT) void k_adj_assemble(Grid g, Tiling t, AdjStep S)
+// Transpose of the gradient / Laplacian stencils as a 2.5-D LDS stencil: a
+// workgroup owns a BX x BY column tile and marches up a z-chunk; LDS holds a
+// ring of three planes of the (grad x, y, z; Laplacian) cotangent records with
+// a halo of one.  Same sums as adj_assemble_node.
+template <int BX, int BY>
+__global__ __launch_bounds__(BX *BY) void k_adj_assemble_lds(Grid g, PhaseTiling pt, AdjStep S)
 {
-    const Node nd = tile_node(g, t, xcd_tile(blockIdx.x, t.ntiles));
-    if (nd.in) adj_assemble_node(g, S, nd.x, nd.y, nd.z);
+    constexpr int NT = BX * BY;
+    constexpr int AX = BX + 2, AY = BY + 2;
+    constexpr int PA = (AX * AY + NT - 1) / NT;
+    __shared__ float4 sr[3][AY * AX];
+    const uint32_t tile = xcd_tile(blockIdx.x, pt.ntiles);
+    const int tcx = (int)(tile % (uint32_t)pt.ntx);
+    const int tcy = (int)((tile / (uint32_t)pt.ntx) % (uint32_t)pt.nty);
+    const int tcz = (int)(tile / ((uint32_t)pt.ntx * (uint32_t)pt.nty));
+    const int x0 = tcx * BX, y0 = tcy * BY, z0 = tcz * pt.zc;
+    const int z1 = min(z0 + pt.zc, g.nz);
+    const int tid = threadIdx.x;
+    const int lx = tid % BX, ly = tid / BX;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool col_in = x < g.nx && y < g.ny;
+    const float4 *rec4 = reinterpret_cast<const float4 *>(S.rec);
+    const float *recl = S.rec + 4u * g.N;
+    static_assert(PA <= 2, "two halo points per thread");
+    // this thread's (up to) two halo points of a plane: in-plane global offset
+    const int k0 = tid, k1 = tid + NT;
+    const bool h0 = k0 < AX * AY, h1 = k1 < AX * AY;
+    const uint32_t a0 = h0 ? (uint32_t)wrapc(x0 - 1 + k0 % AX, g.nx) + (uint32_t)wrapc(y0 - 1 + k0 / AX, g.ny) * (uint32_t)g.nx : 0u;
+    const uint32_t a1 = h1 ? (uint32_t)wrapc(x0 - 1 + k1 % AX, g.nx) + (uint32_t)wrapc(y0 - 1 + k1 / AX, g.ny) * (uint32_t)g.nx : 0u;
+    auto slot = [&](int zz) { return (zz - z0 + 4) % 3; };
+    float4 v0 = make_float4(0.f, 0.f, 0.f, 0.f), v1 = v0;
+    auto fetch = [&](int zz) {
+        const uint32_t zo = (uint32_t)wrapc(zz, g.nz) * g.nxny;
+        if (h0) v0 = rec4[a0 + zo];
+        if (h1) v1 = rec4[a1 + zo];
+    };
+    auto store = [&](int zz) {
+        float4 *dst = sr[slot(zz)];
+        if (h0) dst[k0] = v0;
+        if (h1) dst[k1] = v1;
+    };
+    fetch(z0 - 1);
+    store(z0 - 1);
+    fetch(z0);
+    store(z0);
+    fetch(z0 + 1);
+    const int c0 = (ly + 1) * AX + lx + 1;
+    for (int z = z0; z < z1; ++z) {
+        store(z + 1);
+        __syncthreads();
+        if (z + 1 < z1) fetch(z + 2);  // lands while this plane computes
+        if (col_in) {
+            const float L0 = sr[slot(z)][c0].w;
+            float dv = 0.f, lp = 0.f;
+            static_for<27>([&](auto K) {
+                constexpr int kk = K;
+                constexpr int dx = kk % 3 - 1, dy = (kk / 3) % 3 - 1, dz = kk / 9 - 1;
+                if constexpr (kk != 13) {
+                    constexpr float w = tw(dx) * tw(dy) * tw(dz);
+                    const float4 q = sr[slot(z + dz)][c0 + dy * AX + dx];
+                    if constexpr (dx != 0) dv += ((float)dx * w * (1.0f / 72.0f)) * q.x;
+                    if constexpr (dy != 0) dv += ((float)dy * w * (1.0f / 72.0f)) * q.y;
+                    if constexpr (dz != 0) dv += ((float)dz * w * (1.0f / 72.0f)) * q.z;
+                    lp += (w * (1.0f / 36.0f)) * (q.w - L0);
+                }
+            });
+            const uint32_t n = (uint32_t)x + (uint32_t)y * (uint32_t)g.nx + (uint32_t)z * g.nxny;
+            S.pb_out[n] = recl[n] + lp - dv;
+        }
+        __syncthreads();  // the slot of plane z - 1 is overwritten next
+    }
 }
 
 __global__ __launch_bounds__(256) void k_adj_wall(Grid g, DevParams p, AdjStep S)
@@ -164,11 +244,14 @@ uint32_t adj_red_blocks(const Grid &g) { return nblocks(g.N, 256); }
 
 hipError_t launch_adj_vsum(const Grid &g, const DevParams &p, const AdjStep &S, hipStream_t s)
 {
-    const unsigned nb = nblocks(g.N, 256);
-    k_adj_vsum<<<nb, 256, 0, s>>>(g.N, S.solid, S.pb_in, S.phistar, p.eps_phi, S.red);
+    const unsigned nr = nblocks(g.N, 256 * ADJ_VSUM_PER_THREAD);
+    k_adj_vsum<<<nr, 256, 0, s>>>(g.N, S.solid, S.pb_in, S.phistar, p.eps_phi, S.red);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_adj_vfin<<<1, 1024, 0, s>>>(S.red, nb, S.scal, S.rs, p.volume_correction);
+    k_adj_vfin<<<1, 1024, 0, s>>>(S.red, nr, S.scal, S.rs, p.volume_correction);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_adj_psi<<<nblocks(g.N, 256), 256, 0, s>>>(g.N, p, S);
     return hipGetLastError();
 }
 
@@ -185,11 +268,13 @@ hipError_t launch_adj_main(const Grid &g, const Tiling &t, const DevParams &p, c
 
 hipError_t launch_adj_assemble(const Grid &g, const Tiling &t, const AdjStep &S, hipStream_t s)
 {
-    switch (t.bx * t.by * t.bz) {
-    case 128: k_adj_assemble<128><<<t.ntiles, 128, 0, s>>>(g, t, S); break;
-    case 256: k_adj_assemble<256><<<t.ntiles, 256, 0, s>>>(g, t, S); break;
-    case 512: k_adj_assemble<512><<<t.ntiles, 512, 0, s>>>(g, t, S); break;
-    default: return hipErrorInvalidValue;
+    (void)t;
+    if (g.nx >= 64) {
+        const PhaseTiling pt = phase_tiling(g, 64, 4);
+        k_adj_assemble_lds<64, 4><<<pt.ntiles, 256, 0, s>>>(g, pt, S);
+    } else {
+        const PhaseTiling pt = phase_tiling(g, 16, 16);
+        k_adj_assemble_lds<16, 16><<<pt.ntiles, 256, 0, s>>>(g, pt, S);
     }
     return hipGetLastError();
 }

@@ -30,6 +30,19 @@ namespace cac {
 
 #define CAC_HD __host__ __device__ __forceinline__
 
+// Scheduling fence for the device pass: keeps the compiler from hoisting every
+// load of the node body to its start (which would need more than 128 VGPRs).
+// CAC_PIN(v) makes the value v exist at that point of the program (an empty
+// asm statement reads and writes it), so that the arithmetic feeding it is
+// not sunk below later loads.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define CAC_SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
+#define CAC_PIN(v) asm volatile("" : "+v"(v))
+#else
+#define CAC_SCHED_FENCE() ((void)0)
+#define CAC_PIN(v) ((void)0)
+#endif
+
 // Transpose of phi^{n+1} = phi* + lambda chi(phi*) on fluid nodes, with
 // lambda = (M - sum phi*) / sum chi (Eqs. (49)-(55)):
 //   psi = (1 + lambda chi'(phi*)) (pb - cbar),   cbar = sum(pb chi) / sum chi.
@@ -37,6 +50,12 @@ CAC_HD float psi_of(float pb, float ps, float lam, float cb, float eps)
 {
     const float chip = (ps > eps && ps < 1.0f - eps) ? 1.0f - 2.0f * ps : 0.0f;
     return (1.0f + lam * chip) * (pb - cb);
+}
+
+// psi field of one reverse step: the cotangent of phi* on fluid nodes, 0 on solid nodes.
+CAC_HD void adj_psi_node(const DevParams &p, const AdjStep &S, uint32_t n)
+{
+    S.psi[n] = S.solid[n] ? 0.0f : psi_of(S.pb_in[n], S.phistar[n], (float)S.rs[0], (float)S.rs[1], p.eps_phi);
 }
 
 // Isotropic gradient (Eq. (22)) of a 3x3x3 patch v[k], k = (dz+1)*9 + (dy+1)*3 + (dx+1),
@@ -99,46 +118,92 @@ CAC_HD float muscl_axis_adj(const float (&q)[5], const float (&uu)[5], const flo
     return r;
 }
 
-// Cotangent of a pulled population f_i from the ten moment cotangents
-// (p*, j_x, j_y, j_z, P_xx, P_yy, P_zz, P_xy, P_xz, P_yz).
-template <int I, class L>
-CAC_HD float pop_bar(L &&mbv)
+// Cotangent of a pulled population f_i from the ten moment cotangents, held as
+// a = (p*, j_x, j_y, j_z), b = (P_xx, P_yy, P_zz, P_xy), c = (P_xz, P_yz).
+template <int I>
+CAC_HD float pop_bar(float4 a, float4 b, float2 c)
 {
     constexpr int cx = Lat::cx[I], cy = Lat::cy[I], cz = Lat::cz[I];
-    float v = mbv(0);
-    if constexpr (cx != 0) v += (float)cx * mbv(1) + mbv(4);
-    if constexpr (cy != 0) v += (float)cy * mbv(2) + mbv(5);
-    if constexpr (cz != 0) v += (float)cz * mbv(3) + mbv(6);
-    if constexpr (cx * cy != 0) v += (float)(cx * cy) * mbv(7);
-    if constexpr (cx * cz != 0) v += (float)(cx * cz) * mbv(8);
-    if constexpr (cy * cz != 0) v += (float)(cy * cz) * mbv(9);
+    float v = a.x;
+    if constexpr (cx != 0) v += (float)cx * a.y + b.x;
+    if constexpr (cy != 0) v += (float)cy * a.z + b.y;
+    if constexpr (cz != 0) v += (float)cz * a.w + b.z;
+    if constexpr (cx * cy != 0) v += (float)(cx * cy) * b.w;
+    if constexpr (cx * cz != 0) v += (float)(cx * cz) * c.x;
+    if constexpr (cy * cz != 0) v += (float)(cy * cz) * c.y;
     return v;
 }
 
+// Cotangents of the Hermite coefficients of the post-collision populations
+// (the C2 trace is folded into xx, yy, zz).
+struct HermBar {
+    float ps = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
+    float xx = 0.f, yy = 0.f, zz = 0.f, xy = 0.f, xz = 0.f, yz = 0.f;
+    float xxy = 0.f, xxz = 0.f, yyx = 0.f, yyz = 0.f, zzx = 0.f, zzy = 0.f, xyz = 0.f;
+    CAC_HD void pin()
+    {
+        CAC_PIN(ps); CAC_PIN(bx); CAC_PIN(by); CAC_PIN(bz);
+        CAC_PIN(xx); CAC_PIN(yy); CAC_PIN(zz); CAC_PIN(xy); CAC_PIN(xz); CAC_PIN(yz);
+        CAC_PIN(xxy); CAC_PIN(xxz); CAC_PIN(yyx); CAC_PIN(yyz); CAC_PIN(zzx); CAC_PIN(zzy); CAC_PIN(xyz);
+    }
+};
+
+// Transpose of the Hermite projection of one post-collision population
+// f*_i = w_i [ps + 3 c.b + 4.5 (cc : C2 - tr C2 / 3) + 4.5 H3 : C3] (herm_pair):
+// adds fb * d f*_i / d (coefficients).
+template <int I>
+CAC_HD void proj_add(float fb, HermBar &h)
+{
+    constexpr float cx = (float)Lat::cx[I], cy = (float)Lat::cy[I], cz = (float)Lat::cz[I];
+    constexpr float w = Lat::w(I);
+    constexpr float t2 = 4.5f * w;
+    constexpr float hx = cx * cx - 1.0f / 3.0f, hy = cy * cy - 1.0f / 3.0f, hz = cz * cz - 1.0f / 3.0f;
+    h.ps += w * fb;
+    h.xx += (t2 * hx) * fb;  // cc : C2 - tr/3 = sum_a (c_a^2 - 1/3) C2_aa + off-diagonal terms
+    h.yy += (t2 * hy) * fb;
+    h.zz += (t2 * hz) * fb;
+    if constexpr (cx * cy != 0.0f) h.xy += (2.0f * t2 * cx * cy) * fb;
+    if constexpr (cx * cz != 0.0f) h.xz += (2.0f * t2 * cx * cz) * fb;
+    if constexpr (cy * cz != 0.0f) h.yz += (2.0f * t2 * cy * cz) * fb;
+    if constexpr (cx != 0.0f) h.bx += (3.0f * w * cx) * fb;
+    if constexpr (cy != 0.0f) h.by += (3.0f * w * cy) * fb;
+    if constexpr (cz != 0.0f) h.bz += (3.0f * w * cz) * fb;
+    if constexpr (hx * cy != 0.0f) h.xxy += (3.0f * t2 * hx * cy) * fb;
+    if constexpr (hx * cz != 0.0f) h.xxz += (3.0f * t2 * hx * cz) * fb;
+    if constexpr (hy * cx != 0.0f) h.yyx += (3.0f * t2 * hy * cx) * fb;
+    if constexpr (hy * cz != 0.0f) h.yyz += (3.0f * t2 * hy * cz) * fb;
+    if constexpr (hz * cx != 0.0f) h.zzx += (3.0f * t2 * hz * cx) * fb;
+    if constexpr (hz * cy != 0.0f) h.zzy += (3.0f * t2 * hz * cy) * fb;
+    if constexpr (cx * cy * cz != 0.0f) h.xyz += (6.0f * t2 * cx * cy * cz) * fb;
+}
+
+// Moments (p*, j, P = sum f c c) of the pulled populations, added one population at a time.
+template <int I>
+CAC_HD void moment_add(float v, float (&mom)[10])
+{
+    constexpr int cx = Lat::cx[I], cy = Lat::cy[I], cz = Lat::cz[I];
+    mom[0] += v;
+    if constexpr (cx != 0) { mom[1] += (float)cx * v; mom[4] += v; }
+    if constexpr (cy != 0) { mom[2] += (float)cy * v; mom[5] += v; }
+    if constexpr (cz != 0) { mom[3] += (float)cz * v; mom[6] += v; }
+    if constexpr (cx * cy != 0) mom[7] += (float)(cx * cy) * v;
+    if constexpr (cx * cz != 0) mom[8] += (float)(cx * cz) * v;
+    if constexpr (cy * cz != 0) mom[9] += (float)(cy * cz) * v;
+}
+
 // Transpose of the collision of hydro_node at one fluid node.
-// f: pulled populations; (gx, gy, gz, lap, ph): phi-hat gradient, Laplacian and
-// value; fb: cotangent of the post-collision populations; (ubx, uby, ubz):
+// mom: moments (p*, j, P) of the pulled populations; (gx, gy, gz, lap, ph):
+// phi-hat gradient, Laplacian and value; hb: cotangents of the Hermite
+// coefficients of the post-collision populations (proj_add); (ubx, uby, ubz):
 // cotangent of the velocity output.  Writes the moment cotangents mb and adds
 // the cotangents of ph, of the gradient and of the Laplacian.
-CAC_HD void collide_adj(const DevParams &p, const float (&f)[27], float gx, float gy, float gz, float lap, float ph,
-                        const float (&fb)[27], float ubx, float uby, float ubz, float (&mb)[10], float &phb,
+CAC_HD void collide_adj(const DevParams &p, const float (&mom)[10], float gx, float gy, float gz, float lap, float ph,
+                        const HermBar &hb, float ubx, float uby, float ubz, float (&mb)[10], float &phb,
                         float &Gbx, float &Gby, float &Gbz, float &lapb)
 {
     // ---------------- forward recompute, in the order of hydro_node
-    float ps = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
-    float Pxx = 0.f, Pyy = 0.f, Pzz = 0.f, Pxy = 0.f, Pxz = 0.f, Pyz = 0.f;
-    static_for<27>([&](auto I) {
-        constexpr int i = I;
-        constexpr float cx = (float)Lat::cx[i], cy = (float)Lat::cy[i], cz = (float)Lat::cz[i];
-        const float v = f[i];
-        ps += v;
-        if constexpr (Lat::cx[i] != 0) { jx += cx * v; Pxx += v; }
-        if constexpr (Lat::cy[i] != 0) { jy += cy * v; Pyy += v; }
-        if constexpr (Lat::cz[i] != 0) { jz += cz * v; Pzz += v; }
-        if constexpr (Lat::cx[i] * Lat::cy[i] != 0) Pxy += cx * cy * v;
-        if constexpr (Lat::cx[i] * Lat::cz[i] != 0) Pxz += cx * cz * v;
-        if constexpr (Lat::cy[i] * Lat::cz[i] != 0) Pyz += cy * cz * v;
-    });
+    const float ps = mom[0], jx = mom[1], jy = mom[2], jz = mom[3];
+    const float Pxx = mom[4], Pyy = mom[5], Pzz = mom[6], Pxy = mom[7], Pxz = mom[8], Pyz = mom[9];
     const float mu_phi = p.beta4 * ph * (ph - 1.0f) * (ph - 0.5f) - p.kappa_phi * lap;
     const float F0x = mu_phi * gx, F0y = mu_phi * gy, F0z = mu_phi * gz;
     const float rho = p.rho_g + p.drho * ph;
@@ -188,42 +253,10 @@ CAC_HD void collide_adj(const DevParams &p, const float (&f)[27], float gx, floa
     const float A2yz = Pyz - uy * uz + 0.5f * (uy * az + ay * uz);
     const float om1 = 1.0f - omega;
 
-    // ---------------- transpose of the Hermite projection (herm_pair and the rest population)
-    float hps = Lat::w(0) * fb[0], htr = -4.5f * Lat::w(0) * fb[0];
-    float hbx = 0.f, hby = 0.f, hbz = 0.f;
-    float hxx = 0.f, hyy = 0.f, hzz = 0.f, hxy = 0.f, hxz = 0.f, hyz = 0.f;
-    float hxxy = 0.f, hxxz = 0.f, hyyx = 0.f, hyyz = 0.f, hzzx = 0.f, hzzy = 0.f, hxyz = 0.f;
-    static_for<13>([&](auto P) {
-        constexpr int i = 2 * P + 1;
-        constexpr float cx = (float)Lat::cx[i], cy = (float)Lat::cy[i], cz = (float)Lat::cz[i];
-        constexpr float w = Lat::w(i);
-        constexpr float hx = cx * cx - 1.0f / 3.0f, hy = cy * cy - 1.0f / 3.0f, hz = cz * cz - 1.0f / 3.0f;
-        const float Eb = fb[i] + fb[i + 1], Ob = fb[i] - fb[i + 1];
-        hps += w * Eb;
-        const float te = (4.5f * w) * Eb;
-        htr -= te;
-        hxx += (cx * cx) * te;
-        hyy += (cy * cy) * te;
-        hzz += (cz * cz) * te;
-        hxy += (2.0f * cx * cy) * te;
-        hxz += (2.0f * cx * cz) * te;
-        hyz += (2.0f * cy * cz) * te;
-        const float to = (3.0f * w) * Ob;
-        hbx += cx * to;
-        hby += cy * to;
-        hbz += cz * to;
-        const float t3 = (4.5f * w) * Ob;
-        hxxy += (3.0f * hx * cy) * t3;
-        hxxz += (3.0f * hx * cz) * t3;
-        hyyx += (3.0f * hy * cx) * t3;
-        hyyz += (3.0f * hy * cz) * t3;
-        hzzx += (3.0f * hz * cx) * t3;
-        hzzy += (3.0f * hz * cy) * t3;
-        hxyz += (6.0f * cx * cy * cz) * t3;
-    });
-    hxx += htr * (1.0f / 3.0f);  // tr3 = (C2_xx + C2_yy + C2_zz) / 3
-    hyy += htr * (1.0f / 3.0f);
-    hzz += htr * (1.0f / 3.0f);
+    const float hps = hb.ps, hbx = hb.bx, hby = hb.by, hbz = hb.bz;
+    const float hxx = hb.xx, hyy = hb.yy, hzz = hb.zz, hxy = hb.xy, hxz = hb.xz, hyz = hb.yz;
+    const float hxxy = hb.xxy, hxxz = hb.xxz, hyyx = hb.yyx, hyyz = hb.yyz, hzzx = hb.zzx, hzzy = hb.zzy,
+                hxyz = hb.xyz;
 
     // ---------------- back through C2, C3 and b = u + a/2
     float Ubx = ubx + hbx, Uby = uby + hby, Ubz = ubz + hbz;
@@ -370,39 +403,43 @@ CAC_HD void adj_main_node(const Grid &g, const DevParams &p, const AdjStep &S, i
     const uint32_t m = S.nbr[n];
     const uint32_t N = g.N;
     const bool sol = (m & 1u) != 0;
-    const float lam = (float)S.rs[0], cb = (float)S.rs[1];
-    const float eps = p.eps_phi;
-    auto psi = [&](uint32_t id) { return psi_of(S.pb_in[id], S.phistar[id], lam, cb, eps); };
-
-    // psi on the fluid nodes of the 3x3x3 patch, zero on solid nodes
+    float4 *rec4 = reinterpret_cast<float4 *>(S.rec);  // (grad x, y, z; Laplacian) cotangents
+    float *recl = S.rec + 4u * N;                       // local cotangent of phi-hat
+    if (sol && !((~m) & 0x07FFFFFEu)) {  // solid node without fluid neighbours: pass-through only
+        rec4[n] = make_float4(0.f, 0.f, 0.f, 0.f);
+        recl[n] = S.pb_in[n];
+        return;
+    }
+    // psi on the 3x3x3 patch (zero on solid nodes)
     float pf[27];
     static_for<27>([&](auto K) {
         constexpr int kk = K;
-        constexpr int dx = kk % 3 - 1, dy = (kk / 3) % 3 - 1, dz = kk / 9 - 1;
-        constexpr int li = Lat::idx(dx, dy, dz);
-        pf[kk] = ((m >> li) & 1u) ? 0.0f : psi(at<dx, dy, dz>(o));
+        pf[kk] = S.psi[at<kk % 3 - 1, (kk / 3) % 3 - 1, kk / 9 - 1>(o)];
     });
-    if (sol && !((~m) & 0x07FFFFFEu)) {  // solid node without fluid neighbours: pass-through only
-        S.rec[n] = 0.f;
-        S.rec[N + n] = 0.f;
-        S.rec[2u * N + n] = 0.f;
-        S.rec[3u * N + n] = 0.f;
-        S.rec[4u * N + n] = S.pb_in[n];
-        return;
-    }
     // cotangent of the compressive flux a here: the transpose of -kappa div_iso(a) is kappa grad_iso(psi_f)
     float agx, agy, agz;
     patch_grad(pf, agx, agy, agz);
     agx *= p.kappa;
     agy *= p.kappa;
     agz *= p.kappa;
+    CAC_PIN(agx);
+    CAC_PIN(agy);
+    CAC_PIN(agz);
+    CAC_SCHED_FENCE();
 
-    // phi-hat patch
+    // phi-hat patch, its gradient and Laplacian (used on fluid nodes)
     float s[27];
     static_for<27>([&](auto K) {
         constexpr int kk = K;
         s[kk] = S.phihat[at<kk % 3 - 1, (kk / 3) % 3 - 1, kk / 9 - 1>(o)];
     });
+    float gx, gy, gz, lap;
+    stencil_grad_lap(s, gx, gy, gz, lap);
+    CAC_PIN(gx);
+    CAC_PIN(gy);
+    CAC_PIN(gz);
+    CAC_PIN(lap);
+    CAC_SCHED_FENCE();
 
     // identity part of P and V (solid nodes keep phi-hat: pass-through)
     float phb = sol ? S.pb_in[n] : pf[13];
@@ -437,11 +474,14 @@ CAC_HD void adj_main_node(const Grid &g, const DevParams &p, const AdjStep &S, i
                 } else {
                     q[k] = S.phihat[id];
                     fl[k] = S.solid[id] == 0;
-                    pp[k] = fl[k] ? psi(id) : 0.0f;
+                    pp[k] = S.psi[id];
                 }
                 uu[k] = S.u[(uint32_t)d * N + id];
             }
             phb += muscl_axis_adj(q, uu, pp, fl, ub[d]);
+            CAC_PIN(phb);
+            CAC_PIN(ub[d]);
+            CAC_SCHED_FENCE();
         }
     }
     if (sol) {
@@ -450,16 +490,11 @@ CAC_HD void adj_main_node(const Grid &g, const DevParams &p, const AdjStep &S, i
             S.awb[N + n] = agy;
             S.awb[2u * N + n] = agz;
         }
-        S.rec[n] = 0.f;
-        S.rec[N + n] = 0.f;
-        S.rec[2u * N + n] = 0.f;
-        S.rec[3u * N + n] = 0.f;
-        S.rec[4u * N + n] = phb;
+        rec4[n] = make_float4(0.f, 0.f, 0.f, 0.f);
+        recl[n] = phb;
         return;
     }
 
-    float gx, gy, gz, lap;
-    stencil_grad_lap(s, gx, gy, gz, lap);
     const float ph = s[13];
     float Gbx = 0.f, Gby = 0.f, Gbz = 0.f;
     // compressive flux a = phi (1 - phi) grad / |grad| (Eq. (25)), zero under the guard
@@ -480,45 +515,57 @@ CAC_HD void adj_main_node(const Grid &g, const DevParams &p, const AdjStep &S, i
     // diffusion D lap(phi): the Laplacian stencil is symmetric
     float lapb = p.D * pf[13];
 
-    // cotangent of the post-collision populations: transpose of the pull with
-    // bounce-back, f_i(x + c_i) <- f*_i(x) if x + c_i is fluid, else f_opp(i)(x) <- f*_i(x)
-    float mbx[10];
-#pragma unroll
-    for (int k = 0; k < 10; ++k) mbx[k] = S.mb_in[(uint32_t)k * N + n];
-    float fb[27];
-    fb[0] = mbx[0];
-    static_for<26>([&](auto J) {
-        constexpr int i = J + 1;
-        constexpr int oi = Lat::opp(i);
-        if ((m >> i) & 1u) {
-            fb[i] = pop_bar<oi>([&](int k) { return mbx[k]; });
-        } else {
-            const uint32_t id = at<Lat::cx[i], Lat::cy[i], Lat::cz[i]>(o);
-            fb[i] = pop_bar<i>([&](int k) { return S.mb_in[(uint32_t)k * N + id]; });
-        }
-    });
-    // pulled populations of the step (as hydro_node)
-    float f[27];
+    CAC_SCHED_FENCE();
+    // moments of the pulled populations of the step (as hydro_node)
+    float mom[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     static_for<27>([&](auto I) {
         constexpr int i = I;
         if constexpr (i == 0) {
-            f[0] = S.fprev[n];
+            moment_add<0>(S.fprev[n], mom);
         } else {
             constexpr int ob = Lat::opp(i);
             const uint32_t src = at<Lat::cx[ob], Lat::cy[ob], Lat::cz[ob]>(o);
             const bool wall = (m >> ob) & 1u;
-            f[i] = S.fprev[wall ? (uint32_t)ob * N + n : (uint32_t)i * N + src];
+            moment_add<i>(S.fprev[wall ? (uint32_t)ob * N + n : (uint32_t)i * N + src], mom);
         }
     });
-    float mbo[10];
-    collide_adj(p, f, gx, gy, gz, lap, ph, fb, ub[0], ub[1], ub[2], mbo, phb, Gbx, Gby, Gbz, lapb);
+    // cotangent of the post-collision populations: transpose of the pull with
+    // bounce-back (f_i(x + c_i) <- f*_i(x) if x + c_i is fluid, else
+    // f_opp(i)(x) <- f*_i(x)), projected on the Hermite coefficients as it is gathered
 #pragma unroll
-    for (int k = 0; k < 10; ++k) S.mb_out[(uint32_t)k * N + n] = mbo[k];
-    S.rec[n] = Gbx;
-    S.rec[N + n] = Gby;
-    S.rec[2u * N + n] = Gbz;
-    S.rec[3u * N + n] = lapb;
-    S.rec[4u * N + n] = phb;
+    for (int k = 0; k < 10; ++k) CAC_PIN(mom[k]);
+    CAC_SCHED_FENCE();
+    const float4 *mA = reinterpret_cast<const float4 *>(S.mb_in);
+    const float4 *mB = mA + N;
+    const float2 *mC = reinterpret_cast<const float2 *>(S.mb_in + 8u * N);
+    const float4 a0 = mA[n], b0 = mB[n];
+    const float2 c0 = mC[n];
+    HermBar hb;
+    proj_add<0>(a0.x, hb);
+    static_for<26>([&](auto J) {
+        constexpr int i = J + 1;
+        constexpr int oi = Lat::opp(i);
+        // both candidates are formed and the wall bit selects (the neighbour index is valid either way)
+        const uint32_t id = at<Lat::cx[i], Lat::cy[i], Lat::cz[i]>(o);
+        constexpr bool needc = Lat::cz[i] != 0 && (Lat::cx[i] != 0 || Lat::cy[i] != 0);
+        const float2 ci = needc ? mC[id] : make_float2(0.f, 0.f);
+        const float vn = pop_bar<i>(mA[id], mB[id], ci);
+        const float vw = pop_bar<oi>(a0, b0, c0);
+        proj_add<i>(((m >> i) & 1u) ? vw : vn, hb);
+        if constexpr (i % 5 == 0) {
+            hb.pin();
+            CAC_SCHED_FENCE();
+        }
+    });
+    CAC_SCHED_FENCE();
+    float mbo[10];
+    collide_adj(p, mom, gx, gy, gz, lap, ph, hb, ub[0], ub[1], ub[2], mbo, phb, Gbx, Gby, Gbz, lapb);
+    float4 *oA = reinterpret_cast<float4 *>(S.mb_out);
+    oA[n] = make_float4(mbo[0], mbo[1], mbo[2], mbo[3]);
+    oA[N + n] = make_float4(mbo[4], mbo[5], mbo[6], mbo[7]);
+    reinterpret_cast<float2 *>(S.mb_out + 8u * N)[n] = make_float2(mbo[8], mbo[9]);
+    rec4[n] = make_float4(Gbx, Gby, Gbz, lapb);
+    recl[n] = phb;
 }
 
 // Transpose of the gradient and Laplacian stencils: cotangent of phi-hat at
@@ -528,17 +575,20 @@ CAC_HD void adj_assemble_node(const Grid &g, const AdjStep &S, int x, int y, int
     const Offs o = node_offsets(g, x, y, z);
     const uint32_t n = at<0, 0, 0>(o);
     const uint32_t N = g.N;
-    const float L0 = S.rec[3u * N + n];
+    const float4 *rec4 = reinterpret_cast<const float4 *>(S.rec);
+    const float L0 = rec4[n].w;
     float dv = 0.f, lp = 0.f;
     static_for<27>([&](auto K) {
         constexpr int kk = K;
         constexpr int dx = kk % 3 - 1, dy = (kk / 3) % 3 - 1, dz = kk / 9 - 1;
-        constexpr float w = tw(dx) * tw(dy) * tw(dz);
-        const uint32_t id = at<dx, dy, dz>(o);
-        if constexpr (dx != 0) dv += ((float)dx * w * (1.0f / 72.0f)) * S.rec[id];
-        if constexpr (dy != 0) dv += ((float)dy * w * (1.0f / 72.0f)) * S.rec[N + id];
-        if constexpr (dz != 0) dv += ((float)dz * w * (1.0f / 72.0f)) * S.rec[2u * N + id];
-        if constexpr (kk != 13) lp += (w * (1.0f / 36.0f)) * (S.rec[3u * N + id] - L0);
+        if constexpr (kk != 13) {
+            constexpr float w = tw(dx) * tw(dy) * tw(dz);
+            const float4 q = rec4[at<dx, dy, dz>(o)];
+            if constexpr (dx != 0) dv += ((float)dx * w * (1.0f / 72.0f)) * q.x;
+            if constexpr (dy != 0) dv += ((float)dy * w * (1.0f / 72.0f)) * q.y;
+            if constexpr (dz != 0) dv += ((float)dz * w * (1.0f / 72.0f)) * q.z;
+            lp += (w * (1.0f / 36.0f)) * (q.w - L0);
+        }
     });
     S.pb_out[n] = S.rec[4u * N + n] + lp - dv;
 }

@@ -30,7 +30,7 @@ struct AdjTape {
     // reverse state
     bool adj_ready = false;
     float *mb[2] = {nullptr, nullptr}, *pb[2] = {nullptr, nullptr};
-    float *rec = nullptr, *awb = nullptr, *seed = nullptr;
+    float *rec = nullptr, *awb = nullptr, *seed = nullptr, *psi = nullptr;
     double *thb = nullptr, *red = nullptr, *rs = nullptr;
     // donor tables (rebuilt when the geometry changes)
     long long geom_serial = -1;
@@ -96,6 +96,7 @@ cac_status ensure_rings(cac_handle *h, AdjTape &T)
     if (!T.adj_ready) {
         bool ok = alloc_n(h, T.mb[0], 10 * N) && alloc_n(h, T.mb[1], 10 * N) && alloc_n(h, T.pb[0], N) &&
                   alloc_n(h, T.pb[1], N) && alloc_n(h, T.rec, 5 * N) && alloc_n(h, T.awb, 3 * N) &&
+                  alloc_n(h, T.psi, N) &&
                   (T.seed || alloc_n(h, T.seed, N)) &&
                   (T.red || alloc_n(h, T.red, 3 * (size_t)adj_red_blocks(h->g) + 64)) && (T.rs || alloc_n(h, T.rs, 8));
         if (!ok) return fail(h, CAC_ERR_ALLOC, "adjoint buffers");
@@ -161,6 +162,7 @@ cac_status reverse_step(cac_handle *h, AdjTape &T, int j, int c)
     S.mb_in = T.mb[c];
     S.pb_out = T.pb[c ^ 1];
     S.mb_out = T.mb[c ^ 1];
+    S.psi = T.psi;
     S.rec = T.rec;
     S.awb = T.awb;
     S.nbr = h->F.nbr;

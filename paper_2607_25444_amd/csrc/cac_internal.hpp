@@ -173,10 +173,12 @@ struct AdjStep {
     const float *phistar;  // phase field before the volume correction (fluid nodes)
     // cotangents
     const float *pb_in;    // of phi^{n+1} (all nodes)
-    const float *mb_in;    // 10 planes: of the moments of step n+1
+    const float *mb_in;    // of the moments of step n+1: N float4 (p*, j), N float4 (P_xx, P_yy, P_zz, P_xy),
+                           // N float2 (P_xz, P_yz)
+    float *psi;            // of phi* on fluid nodes (0 on solid nodes)
     float *pb_out;         // of phi-hat, then (after the wall pass) of phi^n
-    float *mb_out;         // 10 planes: of the moments of step n
-    float *rec;            // 5 planes: stencil cotangents (grad x,y,z; Laplacian; local)
+    float *mb_out;         // of the moments of step n (layout of mb_in)
+    float *rec;            // N float4 (cotangents of grad x, y, z and of the Laplacian), then N floats (local)
     float *awb;            // 3 planes: of the compressive flux on wall nodes
     // geometry
     const uint32_t *nbr;
@@ -199,6 +201,7 @@ struct AdjStep {
 hipError_t launch_volume_copy(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F,
                               const float *phistar, const float *phihat, float *out, hipStream_t s);
 uint32_t adj_red_blocks(const Grid &g);  // partial entries (3 doubles each) of the reductions
+// reduction of the correction's transpose (lambda, cbar into S.rs) and the psi field
 hipError_t launch_adj_vsum(const Grid &g, const DevParams &p, const AdjStep &S, hipStream_t s);
 hipError_t launch_adj_main(const Grid &g, const Tiling &t, const DevParams &p, const AdjStep &S, hipStream_t s);
 hipError_t launch_adj_assemble(const Grid &g, const Tiling &t, const AdjStep &S, hipStream_t s);

@@ -66,7 +66,7 @@ extern "C" int emu_reverse_step(int nx, int ny, int nz, const double *prm, const
     }
     DonorTables D;
     build_donor_tables(g, widx, wdonor, nwall, D);
-    std::vector<float> rec(5 * (size_t)N, 0.f), awb(3 * (size_t)N, 0.f);
+    std::vector<float> rec(5 * (size_t)N, 0.f), awb(3 * (size_t)N, 0.f), psi(N, 0.f);
     std::vector<float4> dg(D.don_node.size() + 1);
     double rs[4] = {0, 0, 0, 0}, scal[8] = {M_target, 0, 0, 0, 0, 0, 0, 0};
     // V transpose sums
@@ -87,11 +87,12 @@ extern "C" int emu_reverse_step(int nx, int ny, int nz, const double *prm, const
     AdjStep S{};
     S.fprev = fprev; S.phihat = phihat; S.phiold = phiold; S.u = u; S.phistar = phistar;
     S.pb_in = pb_in; S.mb_in = mb_in; S.pb_out = pb_out; S.mb_out = mb_out;
-    S.rec = rec.data(); S.awb = awb.data(); S.nbr = nbr.data(); S.solid = solid;
+    S.rec = rec.data(); S.awb = awb.data(); S.psi = psi.data(); S.nbr = nbr.data(); S.solid = solid;
     S.widx = widx; S.wq = wq.data(); S.wn = wn.data(); S.theta = theta;
     S.don_start = D.don_start.data(); S.don_wall = D.don_wall.data(); S.don_node = D.don_node.data();
     S.ndon = (int)D.don_node.size(); S.don_map = D.don_map.data(); S.dg = dg.data();
     S.near = D.near.data(); S.nnear = (uint32_t)D.near.size(); S.thb = thb; S.rs = rs; S.scal = scal;
+    for (uint32_t n = 0; n < N; ++n) adj_psi_node(p, S, n);
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) adj_main_node(g, p, S, x, y, z);
