@@ -38,10 +38,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+HYDRO_SOURCES = ("kernels.hip", "step_device.hpp", "cac_internal.hpp")
+
+
 def kernel_source_hash():
+    """sha256[:16] over the sources that define the hydrodynamic kernel."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2607_25444_amd", "csrc", "kernels.hip"), "rb") as f:
-        h.update(f.read())
+    for name in HYDRO_SOURCES:
+        with open(os.path.join(ROOT, "paper_2607_25444_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -221,7 +226,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="spreading", choices=["spreading", "orifice", "sessile"])
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default=None, help="bx,by,bz,graph,phase_tile")
     ap.add_argument("--batch-steps", type=int, default=200)
