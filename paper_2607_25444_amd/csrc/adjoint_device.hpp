@@ -521,12 +521,12 @@ CAC_HD void adj_main_node(const Grid &g, const DevParams &p, const AdjStep &S, i
     static_for<27>([&](auto I) {
         constexpr int i = I;
         if constexpr (i == 0) {
-            moment_add<0>(S.fprev[n], mom);
+            moment_add<0>(__builtin_nontemporal_load(&S.fprev[n]), mom);
         } else {
             constexpr int ob = Lat::opp(i);
             const uint32_t src = at<Lat::cx[ob], Lat::cy[ob], Lat::cz[ob]>(o);
             const bool wall = (m >> ob) & 1u;
-            moment_add<i>(S.fprev[wall ? (uint32_t)ob * N + n : (uint32_t)i * N + src], mom);
+            moment_add<i>(__builtin_nontemporal_load(&S.fprev[wall ? (uint32_t)ob * N + n : (uint32_t)i * N + src]), mom);
         }
     });
     // cotangent of the post-collision populations: transpose of the pull with

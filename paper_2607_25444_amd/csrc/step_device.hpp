@@ -230,6 +230,9 @@ __device__ __forceinline__ void ghost_node(const Grid &g, const DevParams &p, in
 //     C2 = uu + (ua + au)/2 + (1 - omega) A2,  C3 = uuu + (1 - omega) S(u A2),
 //     A2 = P - p*/3 I - uu + (ua + au)/2  (second moment of f - f^eq + S/2).
 //   Writes f* and u.
+//   Populations are read and written with non-temporal hints: each is touched
+//   once per step and the 27-plane sets are far larger than the caches, so
+//   they should not evict phi, u and the masks, which the stencils re-read.
 __device__ __forceinline__ void hydro_node(const Grid &g, const DevParams &p, const Node &nd,
                                            const float *__restrict__ fin, float *__restrict__ fout,
                                            const float *__restrict__ phi, const uint32_t *__restrict__ nbr,
@@ -251,12 +254,12 @@ __device__ __forceinline__ void hydro_node(const Grid &g, const DevParams &p, co
     static_for<27>([&](auto I) {
         constexpr int i = I;
         if constexpr (i == 0) {
-            f[0] = fin[n];
+            f[0] = __builtin_nontemporal_load(&fin[n]);
         } else {
             constexpr int ob = Lat::opp(i);
             const uint32_t src = at<Lat::cx[ob], Lat::cy[ob], Lat::cz[ob]>(o);  // x - c_i
             const bool wall = (m >> ob) & 1u;
-            f[i] = fin[wall ? (uint32_t)ob * N + n : (uint32_t)i * N + src];
+            f[i] = __builtin_nontemporal_load(&fin[wall ? (uint32_t)ob * N + n : (uint32_t)i * N + src]);
         }
     });
 
@@ -342,13 +345,13 @@ __device__ __forceinline__ void hydro_node(const Grid &g, const DevParams &p, co
     h.zzy = uz * uz * uy + om1 * (2.0f * uz * A2yz + uy * A2zz);
     h.xyz = ux * uy * uz + om1 * (ux * A2yz + uy * A2xz + uz * A2xy);
 
-    fout[n] = Lat::w(0) * (h.ps - 4.5f * h.tr3);
+    __builtin_nontemporal_store(Lat::w(0) * (h.ps - 4.5f * h.tr3), &fout[n]);
     static_for<13>([&](auto P) {
         constexpr int i = 2 * P + 1;
         float E, O;
         herm_pair<i>(h, E, O);
-        fout[(uint32_t)i * N + n] = E + O;
-        fout[(uint32_t)(i + 1) * N + n] = E - O;
+        __builtin_nontemporal_store(E + O, &fout[(uint32_t)i * N + n]);
+        __builtin_nontemporal_store(E - O, &fout[(uint32_t)(i + 1) * N + n]);
     });
 
     u[n] = ux;
