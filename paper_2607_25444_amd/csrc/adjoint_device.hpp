@@ -177,20 +177,6 @@ CAC_HD void proj_add(float fb, HermBar &h)
     if constexpr (cx * cy * cz != 0.0f) h.xyz += (6.0f * t2 * cx * cy * cz) * fb;
 }
 
-// Moments (p*, j, P = sum f c c) of the pulled populations, added one population at a time.
-template <int I>
-CAC_HD void moment_add(float v, float (&mom)[10])
-{
-    constexpr int cx = Lat::cx[I], cy = Lat::cy[I], cz = Lat::cz[I];
-    mom[0] += v;
-    if constexpr (cx != 0) { mom[1] += (float)cx * v; mom[4] += v; }
-    if constexpr (cy != 0) { mom[2] += (float)cy * v; mom[5] += v; }
-    if constexpr (cz != 0) { mom[3] += (float)cz * v; mom[6] += v; }
-    if constexpr (cx * cy != 0) mom[7] += (float)(cx * cy) * v;
-    if constexpr (cx * cz != 0) mom[8] += (float)(cx * cz) * v;
-    if constexpr (cy * cz != 0) mom[9] += (float)(cy * cz) * v;
-}
-
 // Transpose of the collision of hydro_node at one fluid node.
 // mom: moments (p*, j, P) of the pulled populations; (gx, gy, gz, lap, ph):
 // phi-hat gradient, Laplacian and value; hb: cotangents of the Hermite
@@ -207,9 +193,9 @@ CAC_HD void collide_adj(const DevParams &p, const float (&mom)[10], float gx, fl
     const float mu_phi = p.beta4 * ph * (ph - 1.0f) * (ph - 0.5f) - p.kappa_phi * lap;
     const float F0x = mu_phi * gx, F0y = mu_phi * gy, F0z = mu_phi * gz;
     const float rho = p.rho_g + p.drho * ph;
-    const float irho = 1.0f / rho;
+    const float irho = fast_rcp(rho);
     const float nu = (p.mu_g + p.dmu * ph) * irho;
-    const float omega = 1.0f / (0.5f + 3.0f * nu);
+    const float omega = fast_rcp(0.5f + 3.0f * nu);
     const bool vd = p.variable_density != 0;
     float grx = 0.f, gry = 0.f, grz = 0.f, cp = 0.f, Fx = F0x, Fy = F0y, Fz = F0z;
     float u1x = 0.f, u1y = 0.f, u1z = 0.f, Qxx = 0.f, Qyy = 0.f, Qzz = 0.f, Qxy = 0.f, Qxz = 0.f, Qyz = 0.f, cnu = 0.f;
@@ -516,22 +502,18 @@ CAC_HD void adj_main_node(const Grid &g, const DevParams &p, const AdjStep &S, i
     float lapb = p.D * pf[13];
 
     CAC_SCHED_FENCE();
-    // moments of the pulled populations of the step (as hydro_node)
-    float mom[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    static_for<27>([&](auto I) {
-        constexpr int i = I;
-        if constexpr (i == 0) {
-            moment_add<0>(__builtin_nontemporal_load(&S.fprev[n]), mom);
-        } else {
-            constexpr int ob = Lat::opp(i);
-            const uint32_t src = at<Lat::cx[ob], Lat::cy[ob], Lat::cz[ob]>(o);
-            const bool wall = (m >> ob) & 1u;
-            moment_add<i>(__builtin_nontemporal_load(&S.fprev[wall ? (uint32_t)ob * N + n : (uint32_t)i * N + src]), mom);
-        }
+    // moments of the pulled populations of the step, in the pair order of hydro_node
+    float mom[10] = {__builtin_nontemporal_load(&S.fprev[n]), 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    static_for<13>([&](auto P) {
+        constexpr int i = 2 * P + 1;
+        const uint32_t src_i = at<Lat::cx[i + 1], Lat::cy[i + 1], Lat::cz[i + 1]>(o);
+        const float fi = __builtin_nontemporal_load(
+            &S.fprev[((m >> (i + 1)) & 1u) ? (uint32_t)(i + 1) * N + n : (uint32_t)i * N + src_i]);
+        const uint32_t src_o = at<Lat::cx[i], Lat::cy[i], Lat::cz[i]>(o);
+        const float fo = __builtin_nontemporal_load(
+            &S.fprev[((m >> i) & 1u) ? (uint32_t)i * N + n : (uint32_t)(i + 1) * N + src_o]);
+        pair_moment_add<i>(fi, fo, mom);
     });
-    // cotangent of the post-collision populations: transpose of the pull with
-    // bounce-back (f_i(x + c_i) <- f*_i(x) if x + c_i is fluid, else
-    // f_opp(i)(x) <- f*_i(x)), projected on the Hermite coefficients as it is gathered
 #pragma unroll
     for (int k = 0; k < 10; ++k) CAC_PIN(mom[k]);
     CAC_SCHED_FENCE();

@@ -217,6 +217,63 @@ __device__ __forceinline__ void ghost_node(const Grid &g, const DevParams &p, in
     }
 }
 
+// 1/x: the hardware reciprocal (1 ulp) on the device, a division on the host.
+__host__ __device__ __forceinline__ float fast_rcp(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+
+// Pull of the populations that stream into node n (Sec. II A): f_i(x) =
+// f*_i(x - c_i), or f*_opp(i)(x) when x - c_i is solid (halfway bounce-back),
+// taken pair by pair (i, opp(i) = i + 1).  Non-temporal: each population is
+// read once per step.
+__device__ __forceinline__ void pull_populations(const Grid &g, const Offs &o, uint32_t n, uint32_t m,
+                                                 const float *__restrict__ fin, float (&f)[27])
+{
+    const uint32_t N = g.N;
+    f[0] = __builtin_nontemporal_load(&fin[n]);
+    static_for<13>([&](auto P) {
+        constexpr int i = 2 * P + 1;
+        const uint32_t src_i = at<Lat::cx[i + 1], Lat::cy[i + 1], Lat::cz[i + 1]>(o);
+        f[i] = __builtin_nontemporal_load(&fin[((m >> (i + 1)) & 1u) ? (uint32_t)(i + 1) * N + n : (uint32_t)i * N + src_i]);
+        const uint32_t src_o = at<Lat::cx[i], Lat::cy[i], Lat::cz[i]>(o);
+        f[i + 1] = __builtin_nontemporal_load(&fin[((m >> i) & 1u) ? (uint32_t)i * N + n : (uint32_t)(i + 1) * N + src_o]);
+    });
+}
+
+// Moments p* = sum f, j = sum f c, P = sum f c c (Eqs. (6)-(7)) over the opposite
+// pairs: with s = f_i + f_opp and d = f_i - f_opp, j takes +-d and P takes s.
+// mom = (p*, j_x, j_y, j_z, P_xx, P_yy, P_zz, P_xy, P_xz, P_yz), started at
+// (f_0, 0, ...) and updated pair by pair in the order i = 1, 3, ..., 25.
+template <int I>
+__host__ __device__ __forceinline__ void pair_moment_add(float fi, float fo, float (&mom)[10])
+{
+    constexpr int cx = Lat::cx[I], cy = Lat::cy[I], cz = Lat::cz[I];
+    const float sm = fi + fo, df = fi - fo;
+    mom[0] += sm;
+    if constexpr (cx != 0) { mom[1] += (float)cx * df; mom[4] += sm; }
+    if constexpr (cy != 0) { mom[2] += (float)cy * df; mom[5] += sm; }
+    if constexpr (cz != 0) { mom[3] += (float)cz * df; mom[6] += sm; }
+    if constexpr (cx * cy != 0) mom[7] += (float)(cx * cy) * sm;
+    if constexpr (cx * cz != 0) mom[8] += (float)(cx * cz) * sm;
+    if constexpr (cy * cz != 0) mom[9] += (float)(cy * cz) * sm;
+}
+
+__host__ __device__ __forceinline__ void pair_moments(const float (&f)[27], float (&mom)[10])
+{
+    mom[0] = f[0];
+#pragma unroll
+    for (int k = 1; k < 10; ++k) mom[k] = 0.f;
+    static_for<13>([&](auto P) {
+        constexpr int i = 2 * P + 1;
+        pair_moment_add<i>(f[i], f[i + 1], mom);
+    });
+}
+
 // ------------------------------------------------------------------ H: hydro
 
 // Fused pull collide-stream at fluid node x (Sec. II A):
@@ -251,45 +308,25 @@ __device__ __forceinline__ void hydro_node(const Grid &g, const DevParams &p, co
         s[kk] = phi[at<kk % 3 - 1, (kk / 3) % 3 - 1, kk / 9 - 1>(o)];
     });
     float f[27];
-    static_for<27>([&](auto I) {
-        constexpr int i = I;
-        if constexpr (i == 0) {
-            f[0] = __builtin_nontemporal_load(&fin[n]);
-        } else {
-            constexpr int ob = Lat::opp(i);
-            const uint32_t src = at<Lat::cx[ob], Lat::cy[ob], Lat::cz[ob]>(o);  // x - c_i
-            const bool wall = (m >> ob) & 1u;
-            f[i] = __builtin_nontemporal_load(&fin[wall ? (uint32_t)ob * N + n : (uint32_t)i * N + src]);
-        }
-    });
+    pull_populations(g, o, n, m, fin, f);
 
     float gx, gy, gz, lap;
     stencil_grad_lap(s, gx, gy, gz, lap);
     const float ph = s[13];
 
     // kinetic moments
-    float ps = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
-    float Pxx = 0.f, Pyy = 0.f, Pzz = 0.f, Pxy = 0.f, Pxz = 0.f, Pyz = 0.f;
-    static_for<27>([&](auto I) {
-        constexpr int i = I;
-        constexpr float cx = (float)Lat::cx[i], cy = (float)Lat::cy[i], cz = (float)Lat::cz[i];
-        const float v = f[i];
-        ps += v;
-        if constexpr (Lat::cx[i] != 0) { jx += cx * v; Pxx += v; }
-        if constexpr (Lat::cy[i] != 0) { jy += cy * v; Pyy += v; }
-        if constexpr (Lat::cz[i] != 0) { jz += cz * v; Pzz += v; }
-        if constexpr (Lat::cx[i] * Lat::cy[i] != 0) Pxy += cx * cy * v;
-        if constexpr (Lat::cx[i] * Lat::cz[i] != 0) Pxz += cx * cz * v;
-        if constexpr (Lat::cy[i] * Lat::cz[i] != 0) Pyz += cy * cz * v;
-    });
+    float mom[10];
+    pair_moments(f, mom);
+    const float ps = mom[0], jx = mom[1], jy = mom[2], jz = mom[3];
+    const float Pxx = mom[4], Pyy = mom[5], Pzz = mom[6], Pxy = mom[7], Pxz = mom[8], Pyz = mom[9];
 
     // chemical potential, capillary force, mixture properties
     const float mu_phi = p.beta4 * ph * (ph - 1.0f) * (ph - 0.5f) - p.kappa_phi * lap;
     float Fx = mu_phi * gx, Fy = mu_phi * gy, Fz = mu_phi * gz;
     const float rho = p.rho_g + p.drho * ph;
-    const float irho = 1.0f / rho;
+    const float irho = fast_rcp(rho);
     const float nu = (p.mu_g + p.dmu * ph) * irho;
-    const float omega = 1.0f / (0.5f + 3.0f * nu);
+    const float omega = fast_rcp(0.5f + 3.0f * nu);
     float ax, ay, az;
     if (p.variable_density) {
         const float grx = p.drho * gx, gry = p.drho * gy, grz = p.drho * gz;
@@ -345,6 +382,7 @@ __device__ __forceinline__ void hydro_node(const Grid &g, const DevParams &p, co
     h.zzy = uz * uz * uy + om1 * (2.0f * uz * A2yz + uy * A2zz);
     h.xyz = ux * uy * uz + om1 * (ux * A2yz + uy * A2xz + uz * A2xy);
 
+    const uint32_t n4 = 4u * n, N4 = 4u * N;
     __builtin_nontemporal_store(Lat::w(0) * (h.ps - 4.5f * h.tr3), &fout[n]);
     static_for<13>([&](auto P) {
         constexpr int i = 2 * P + 1;
