@@ -141,26 +141,22 @@ __global__ __launch_bounds__(256) void k_bvol_finalize(BatchPtrs B, const BatchD
     }
 }
 
-// phi <- phi* + lambda_k chi(phi*) on the fluid nodes of the hydro tiles.
-template <int NT>
-__global__ __launch_bounds__(NT) void k_bvol_apply(BatchPtrs B, const BatchDomain *__restrict__ dom,
-                                                   const uint2 *__restrict__ items, uint32_t nitems, int cur_next)
+// phi <- phi* + lambda_k chi(phi*) on fluid nodes (Eq. (53)), one thread per node
+// of the concatenated arrays.  The block's first domain comes from a host-built
+// table; a node past its end belongs to a following domain (a block straddles
+// domains only at their boundaries).
+__global__ __launch_bounds__(256) void k_bvol_apply(BatchPtrs B, const BatchDomain *__restrict__ dom, int cur_next)
 {
-    const ItemRange r = item_range(nitems);
-    for (uint32_t it = r.first; it < r.end; it += r.stride) {
-        const uint2 dt = items[it];
-        const BatchDomain d = dom[dt.x];
-        const Node nd = tile_node(d.g, d.t, dt.y);
-        if (!nd.in) continue;
-        const uint32_t n = (uint32_t)nd.x + (uint32_t)d.g.nx * ((uint32_t)nd.y + (uint32_t)d.g.ny * (uint32_t)nd.z);
-        if (B.solid[d.off + n]) continue;
-        float *phi = (cur_next ? B.phi[1] : B.phi[0]) + d.off;
-        const float v = phi[n];
-        const float eps = d.p.eps_phi;
-        if (v > eps && v < 1.0f - eps) {
-            const double lam = B.scal[8u * dt.x + 1];
-            phi[n] = (float)((double)v + lam * ((double)v * (1.0 - (double)v)));
-        }
+    const uint32_t n = blockIdx.x * 256u + threadIdx.x;
+    if (n >= B.ntot || B.solid[n]) return;
+    uint32_t lo = B.blk_dom[blockIdx.x];
+    while (n >= B.dom_start[lo + 1]) ++lo;
+    float *phi = cur_next ? B.phi[1] : B.phi[0];
+    const float v = phi[n];
+    const float eps = dom[lo].p.eps_phi;
+    if (v > eps && v < 1.0f - eps) {
+        const double lam = B.scal[8u * lo + 1];
+        phi[n] = (float)((double)v + lam * ((double)v * (1.0 - (double)v)));
     }
 }
 
@@ -219,15 +215,14 @@ hipError_t launch_bphase(const BatchPtrs &B, int code, const uint2 *items, uint3
 hipError_t launch_bvolume(const BatchPtrs &B, int nt, const uint2 *items, uint32_t nitems, uint32_t grid, int cur_next,
                           hipStream_t s)
 {
+    (void)nt;
+    (void)items;
+    (void)nitems;
+    (void)grid;
     k_bvol_finalize<<<B.ndom, 256, 0, s>>>(B, B.dom);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !nitems) return e;
-    switch (nt) {
-    case 128: k_bvol_apply<128><<<grid, 128, 0, s>>>(B, B.dom, items, nitems, cur_next); break;
-    case 256: k_bvol_apply<256><<<grid, 256, 0, s>>>(B, B.dom, items, nitems, cur_next); break;
-    case 512: k_bvol_apply<512><<<grid, 512, 0, s>>>(B, B.dom, items, nitems, cur_next); break;
-    default: return hipErrorInvalidValue;
-    }
+    if (e != hipSuccess || !B.ntot) return e;
+    k_bvol_apply<<<(B.ntot + 255u) / 256u, 256, 0, s>>>(B, B.dom, cur_next);
     return hipGetLastError();
 }
 

@@ -443,19 +443,36 @@ cac_status cac_batch_init(cac_batch **bp, int ndom, const cac_domain_desc *d, ca
     B.scal = (double *)balloc(b, 8 * (size_t)ndom * sizeof(double));
     B.flag = (uint32_t *)balloc(b, 256);
     b->d_dom = (BatchDomain *)balloc(b, ndom * sizeof(BatchDomain));
+    uint32_t *d_start = (uint32_t *)balloc(b, (ndom + 1) * sizeof(uint32_t));
+    const size_t nblk = (N + 255) / 256;
+    uint16_t *d_blk = (uint16_t *)balloc(b, nblk * sizeof(uint16_t));
     b->pstar0 = (float *)balloc(b, N * sizeof(float));
     b->mass_partial = (double2 *)balloc(b, (maxN / 256 + 64) * sizeof(double2));
     if (!B.f[0] || !B.f[1] || !B.phi[0] || !B.phi[1] || !B.u || !B.a || !B.nbr || !B.solid || !B.wall_idx ||
         !B.wall_q || !B.wall_n || !B.theta || !B.wall_dom || !B.partial || !B.scal || !B.flag || !b->d_dom ||
-        !b->pstar0 || !b->mass_partial)
+        !b->pstar0 || !b->mass_partial || !d_start || !d_blk)
         return bail(CAC_ERR_ALLOC);
     B.dom = b->d_dom;
+    B.dom_start = d_start;
+    B.blk_dom = d_blk;
+    B.ntot = (uint32_t)N;
     B.ndom = ndom;
     hipStream_t s = b->stream;
     auto up = [&](void *dst, const void *src, size_t bytes) {
         return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
     };
-    if (up(B.nbr, nbr_all.data(), N * sizeof(uint32_t)) != hipSuccess) return bail(CAC_ERR_HIP);
+    std::vector<uint32_t> starts(ndom + 1);
+    for (int k = 0; k < ndom; ++k) starts[k] = b->dom[k].off;
+    starts[ndom] = (uint32_t)N;
+    std::vector<uint16_t> blk(nblk);
+    for (size_t q = 0, k = 0; q < nblk; ++q) {
+        while (256 * q >= starts[k + 1]) ++k;
+        blk[q] = (uint16_t)k;
+    }
+    if (up(B.nbr, nbr_all.data(), N * sizeof(uint32_t)) != hipSuccess ||
+        up(d_start, starts.data(), starts.size() * sizeof(uint32_t)) != hipSuccess ||
+        up(d_blk, blk.data(), blk.size() * sizeof(uint16_t)) != hipSuccess)
+        return bail(CAC_ERR_HIP);
     for (int k = 0; k < ndom; ++k)
         if (up(B.solid + b->dom[k].off, d[k].solid, b->dom[k].g.N) != hipSuccess) return bail(CAC_ERR_HIP);
     if (up(B.wall_idx, widx.data(), widx.size() * 4) != hipSuccess || up(B.wall_q, wq.data(), wq.size()) != hipSuccess ||

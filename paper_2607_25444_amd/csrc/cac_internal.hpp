@@ -123,6 +123,9 @@ struct BatchPtrs {
     double *scal;        // 8 per domain: [0] M_target, [1] lambda, [2] M*, [3] W, [4] volume
     uint32_t *flag;
     const BatchDomain *dom;
+    const uint32_t *dom_start;  // ndom + 1 node offsets: domain k holds nodes [dom_start[k], dom_start[k + 1])
+    const uint16_t *blk_dom;    // domain of the first node of each 256-node block of the concatenated arrays
+    uint32_t ntot;              // total nodes
     int ndom;
 };
 
