@@ -164,6 +164,38 @@ cac_status cac_set_launch(cac_handle *h, int bx, int by, int bz, int phase_tile,
  * V volume correction).  Synchronises.  For measurement only. */
 cac_status cac_profile_step(cac_handle *h, int nsteps, double *ms);
 
+/* Size in bytes of a saved state (cac_save_state): a 64-byte header plus
+ * 33 N floats (populations, phi with the current and the previous ghosts,
+ * velocity, initial p*). */
+cac_status cac_state_bytes(cac_handle *h, size_t *bytes);
+
+/* Checkpoint: copy the complete state (populations, phi and ghosts, velocity,
+ * target volume, step count) into d_buf (device, at least cac_state_bytes).
+ * Synchronises the stream before writing the header.  Errors: CAC_ERR_ARG
+ * (buffer too small), CAC_ERR_STATE (no state, or inside a debug step). */
+cac_status cac_save_state(cac_handle *h, void *d_buf, size_t bytes);
+
+/* Resume from a buffer written by cac_save_state on a handle with the same
+ * lattice size; the geometry and angles are those set on this handle.  Stepping
+ * after a load reproduces the saved run bit for bit.  Discards an adjoint
+ * recording.  Errors: CAC_ERR_ARG (size or header mismatch), CAC_ERR_STATE (no
+ * geometry). */
+cac_status cac_load_state(cac_handle *h, const void *d_buf, size_t bytes);
+
+/* Test hook: run one substep of the next step, in order 0 = W ghost update
+ * (Sec. II B), 1 = H collide-stream (Sec. II A), 2 = P CAC update (Sec. II A 1),
+ * 3 = V volume correction (Sec. II C; completes the step).  cac_step is refused
+ * while a step is partly done.  Errors: CAC_ERR_STATE (out of order). */
+cac_status cac_debug_substep(cac_handle *h, int which);
+
+/* Test hook: copy an internal buffer to d_out (device): 0 = phi of the current
+ * parity (fluid values; after W the new ghosts), 1 = phi of the other parity
+ * (previous ghosts; after P the phase field before the correction), 2 = u (3N),
+ * 3 = populations of the current parity (27N), 4 = populations of the other
+ * parity (after H the post-collision populations, 27N), 5 = compressive flux
+ * on wall nodes (3N).  Errors: CAC_ERR_ARG (unknown buffer). */
+cac_status cac_debug_buffer(cac_handle *h, int which, float *d_out);
+
 /* Release the handle and the device memory it allocated itself. */
 cac_status cac_destroy(cac_handle *h);
 

@@ -60,6 +60,11 @@ SIGNATURES = {
     "cac_set_launch": (C.c_int, [_hp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
     "cac_profile_step": (C.c_int, [_hp, C.c_int, C.POINTER(C.c_double)]),
     "cac_destroy": (C.c_int, [_hp]),
+    "cac_state_bytes": (C.c_int, [_hp, C.POINTER(C.c_size_t)]),
+    "cac_save_state": (C.c_int, [_hp, _vp, C.c_size_t]),
+    "cac_load_state": (C.c_int, [_hp, _vp, C.c_size_t]),
+    "cac_debug_substep": (C.c_int, [_hp, C.c_int]),
+    "cac_debug_buffer": (C.c_int, [_hp, C.c_int, _vp]),
     "cac_tape_forward": (C.c_int, [_hp, C.c_int, C.c_int]),
     "cac_tape_backward": (C.c_int, [_hp, _vp, _vp, _vp]),
     "cac_loss": (C.c_int, [_hp, _vp, _vp, C.POINTER(C.c_double)]),
@@ -270,6 +275,30 @@ class Sim:
         self._check(self.lib.cac_set_launch(self.h, int(bx), int(by), int(bz), int(phase_tile),
                                             int(bool(use_graph))))
         return self
+
+    # -------------------------------------------------------------- checkpoints, test hooks
+    def save_state(self):
+        """Saved state as a new device byte tensor."""
+        nb = C.c_size_t()
+        self._check(self.lib.cac_state_bytes(self.h, C.byref(nb)))
+        buf = self.torch.empty(nb.value, dtype=self.torch.uint8, device=self.device)
+        self._check(self.lib.cac_save_state(self.h, _ptr(buf), nb.value))
+        return buf
+
+    def load_state(self, buf):
+        self._check(self.lib.cac_load_state(self.h, _ptr(buf), buf.numel()))
+        self._keep_loaded = buf
+        return self
+
+    def debug_substep(self, which):
+        self._check(self.lib.cac_debug_substep(self.h, int(which)))
+        return self
+
+    def debug_buffer(self, which):
+        n = {0: 1, 1: 1, 2: 3, 3: 27, 4: 27, 5: 3}[which] * self.N
+        out = self.torch.empty(n, dtype=self.torch.float32, device=self.device)
+        self._check(self.lib.cac_debug_buffer(self.h, int(which), _ptr(out)))
+        return out
 
     # -------------------------------------------------------------- adjoint
     def tape_forward(self, nsteps, K):

@@ -40,6 +40,7 @@ struct cac_handle {
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     hipStream_t cap_stream = nullptr;  // capture needs a stream other than the null stream
     long long geom_serial = 0;   // incremented by every cac_set_geometry
+    int sub = 0;                 // next substep of cac_debug_substep (0 = W ... 3 = V)
     cac::AdjTape *tape = nullptr;  // created by the first recorded sweep
     std::string err;
 };

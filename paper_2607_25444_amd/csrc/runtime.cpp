@@ -466,6 +466,7 @@ cac_status cac_set_state(cac_handle *h, const float *d_phi, const float *d_u, co
     HIPCHK(h, launch_mass(h->g, h->t, F, F.phi[0], F.scal + 0, h->stream));
     h->cur = 0;
     h->steps = 0;
+    h->sub = 0;
     h->state = true;
     tape_invalidate(h);
     return CAC_OK;
@@ -476,6 +477,7 @@ cac_status cac_step(cac_handle *h, int nsteps)
     if (!h) return CAC_ERR_ARG;
     if (nsteps < 0) return fail(h, CAC_ERR_ARG, "nsteps < 0");
     if (!h->state) return fail(h, CAC_ERR_STATE, "cac_set_state must come first");
+    if (h->sub != 0) return fail(h, CAC_ERR_STATE, "a step was started with cac_debug_substep");
     for (int k = 0; k < nsteps; ++k) {
         if (h->use_graph) {
             const int par = h->cur;
@@ -553,6 +555,7 @@ cac_status cac_profile_step(cac_handle *h, int nsteps, double *ms)
 {
     if (!h || !ms || nsteps < 0) return CAC_ERR_ARG;
     if (!h->state) return fail(h, CAC_ERR_STATE, "no state");
+    if (h->sub != 0) return fail(h, CAC_ERR_STATE, "a step was started with cac_debug_substep");
     std::vector<hipEvent_t> ev(5 * (size_t)nsteps);
     for (auto &e : ev) HIPCHK(h, hipEventCreate(&e));
     cac_status st = CAC_OK;
@@ -580,6 +583,115 @@ cac_status cac_profile_step(cac_handle *h, int nsteps, double *ms)
         }
     for (auto &e : ev) (void)hipEventDestroy(e);
     return st;
+}
+
+// ------------------------------------------------------------------ state save / load
+namespace {
+constexpr uint64_t kStateMagic = 0x31455441545343ull;  // "CSTATE1"
+constexpr size_t kStateHeader = 64;
+size_t state_bytes(const cac_handle *h) { return kStateHeader + 33ull * h->g.N * sizeof(float); }
+}  // namespace
+
+cac_status cac_state_bytes(cac_handle *h, size_t *bytes)
+{
+    if (!h || !bytes) return CAC_ERR_ARG;
+    *bytes = state_bytes(h);
+    return CAC_OK;
+}
+
+cac_status cac_save_state(cac_handle *h, void *d_buf, size_t bytes)
+{
+    if (!h || !d_buf) return CAC_ERR_ARG;
+    if (!h->state) return fail(h, CAC_ERR_STATE, "no state");
+    if (h->sub != 0) return fail(h, CAC_ERR_STATE, "a step was started with cac_debug_substep");
+    if (bytes < state_bytes(h)) return fail(h, CAC_ERR_ARG, "buffer of %zu bytes, %zu needed", bytes, state_bytes(h));
+    const size_t N = h->g.N;
+    const int c = h->cur;
+    char *b = (char *)d_buf;
+    uint64_t hdr[3] = {kStateMagic, (uint64_t)N, (uint64_t)h->steps};
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, hipMemcpy(b, hdr, sizeof hdr, hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpyAsync(b + 24, h->F.scal, sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    float *a = (float *)(b + kStateHeader);
+    HIPCHK(h, hipMemcpyAsync(a, h->F.f[c], 27 * N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(a + 27 * N, h->F.phi[c], N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(a + 28 * N, h->F.phi[c ^ 1], N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(a + 29 * N, h->F.u, 3 * N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(a + 32 * N, h->F.pstar0, N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    return CAC_OK;
+}
+
+cac_status cac_load_state(cac_handle *h, const void *d_buf, size_t bytes)
+{
+    if (!h || !d_buf) return CAC_ERR_ARG;
+    if (!h->geometry) return fail(h, CAC_ERR_STATE, "cac_set_geometry must come first");
+    if (bytes < state_bytes(h)) return fail(h, CAC_ERR_ARG, "buffer of %zu bytes, %zu needed", bytes, state_bytes(h));
+    const size_t N = h->g.N;
+    const char *b = (const char *)d_buf;
+    uint64_t hdr[3];
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, hipMemcpy(hdr, b, sizeof hdr, hipMemcpyDeviceToHost));
+    if (hdr[0] != kStateMagic || hdr[1] != (uint64_t)N)
+        return fail(h, CAC_ERR_ARG, "not a saved state of a lattice of this size");
+    const float *a = (const float *)(b + kStateHeader);
+    HIPCHK(h, hipMemcpyAsync(h->F.scal, b + 24, sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->F.f[0], a, 27 * N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->F.phi[0], a + 27 * N, N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->F.phi[1], a + 28 * N, N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->F.u, a + 29 * N, 3 * N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->F.pstar0, a + 32 * N, N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    // the compressive flux is rebuilt by every ghost update; skipped wall nodes keep zero
+    HIPCHK(h, hipMemsetAsync(h->F.a, 0, 3 * N * sizeof(float), h->stream));
+    HIPCHK(h, hipMemsetAsync(h->F.flag, 0, 256, h->stream));
+    h->cur = 0;
+    h->steps = (long long)hdr[2];
+    h->sub = 0;
+    h->state = true;
+    tape_invalidate(h);
+    return CAC_OK;
+}
+
+// ------------------------------------------------------------------ debug hooks
+cac_status cac_debug_substep(cac_handle *h, int which)
+{
+    if (!h) return CAC_ERR_ARG;
+    if (!h->state) return fail(h, CAC_ERR_STATE, "no state");
+    if (which != h->sub) return fail(h, CAC_ERR_STATE, "substep %d expected next, %d requested", h->sub, which);
+    const int c = h->cur;
+    switch (which) {
+    case 0: HIPCHK(h, launch_ghost(h->g, h->dp, h->F, c, h->stream)); break;
+    case 1: HIPCHK(h, launch_hydro(h->g, h->t, h->dp, h->F, c, c, h->stream)); break;
+    case 2: HIPCHK(h, launch_phase(h->g, h->t, h->dp, h->F, c, h->stream)); break;
+    case 3:
+        HIPCHK(h, launch_volume(h->g, h->t, h->dp, h->F, c ^ 1, h->stream));
+        h->cur ^= 1;
+        h->steps++;
+        break;
+    default: return fail(h, CAC_ERR_ARG, "substep %d", which);
+    }
+    h->sub = (which + 1) % 4;
+    return CAC_OK;
+}
+
+cac_status cac_debug_buffer(cac_handle *h, int which, float *d_out)
+{
+    if (!h || !d_out) return CAC_ERR_ARG;
+    if (!h->state) return fail(h, CAC_ERR_STATE, "no state");
+    const size_t N = h->g.N;
+    const int c = h->cur;
+    const float *src = nullptr;
+    size_t n = N;
+    switch (which) {
+    case 0: src = h->F.phi[c]; break;
+    case 1: src = h->F.phi[c ^ 1]; break;
+    case 2: src = h->F.u; n = 3 * N; break;
+    case 3: src = h->F.f[c]; n = 27 * N; break;
+    case 4: src = h->F.f[c ^ 1]; n = 27 * N; break;
+    case 5: src = h->F.a; n = 3 * N; break;
+    default: return fail(h, CAC_ERR_ARG, "buffer %d", which);
+    }
+    HIPCHK(h, hipMemcpyAsync(d_out, src, n * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    return CAC_OK;
 }
 
 cac_status cac_destroy(cac_handle *h)

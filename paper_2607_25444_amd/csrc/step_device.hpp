@@ -540,7 +540,12 @@ __device__ __forceinline__ void phase_tile(const Grid &g, const PhaseTiling &pt,
 
     auto pslot = [&](int zz) { return (zz - z0 + 10) % 5; };
     auto aslot = [&](int zz) { return (zz - z0 + 3) % 3; };
-    auto zoff = [&](int zz) { return (uint32_t)wrapc(zz, g.nz) * g.nxny; };
+    // plane offset with periodic wrap; the planes visited lie within a few of [0, nz),
+    // so the modulo (a long integer division) is taken only off that range
+    auto zoff = [&](int zz) {
+        const int w = (zz >= 0 && zz < g.nz) ? zz : wrapc(zz, g.nz);
+        return (uint32_t)w * g.nxny;
+    };
 
     // this thread's share of the halo planes: global in-plane offset and LDS position
     uint32_t pxy[PF], axy[PA];
