@@ -133,3 +133,17 @@ def test_autotune_keeps_state_and_caches(tmp_path):
     assert len(d["schedules"]) == 1
     b.close()
     b2.close()
+
+
+def test_batch_watchdog():
+    """A NaN in one domain's initial phase field is reported for the batch."""
+    from paper_2607_25444_amd import capi
+    ws = [W.sessile((L, L, L), L / 4.0, 60.0) for L in (16, 24)]
+    ws[1].phi0 = ws[1].phi0.copy()
+    ws[1].phi0[np.flatnonzero(ws[1].solid == 0)[100]] = np.nan
+    b = capi.Batch(ws)
+    b.step(1)
+    with pytest.raises(capi.CacError) as e:
+        b.sync()
+    assert e.value.status == capi.CAC_ERR_NONFINITE
+    b.close()

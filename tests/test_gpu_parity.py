@@ -175,3 +175,32 @@ def test_full_size_spreading_one_step(orc):
     o = oracle_run(orc, w, 1)
     g = gpu_run(w, 1, launch=tuning.launch_for(w.shape))
     _cmp(g, o, w, orc, 2e-6, 1e-5, with_f=False)
+
+
+def test_watchdog_reports_non_finite_values():
+    """A NaN forced into the initial phase field, and a velocity too large for
+    the collision, raise CAC_ERR_NONFINITE at the next synchronising call."""
+    from paper_2607_25444_amd import capi
+    w = W.sessile((24, 20, 16), R=5.0, theta_deg=60.0)
+    fl = np.flatnonzero(w.solid == 0)
+    phi = w.phi0.copy()
+    phi[fl[len(fl) // 2]] = np.nan
+    s = capi.Sim(w.shape, w.params)
+    s.set_geometry(w.solid, w.theta)
+    s.set_state(phi)
+    s.step(1)
+    with pytest.raises(capi.CacError) as e:
+        s.sync()
+    assert e.value.status == capi.CAC_ERR_NONFINITE
+    u0 = np.zeros(3 * w.N, np.float32)
+    u0[fl] = 1e30
+    s.set_state(w.phi0, u0)
+    s.step(2)
+    with pytest.raises(capi.CacError) as e:
+        s.volume()
+    assert e.value.status == capi.CAC_ERR_NONFINITE
+    # a clean state clears the flag
+    s.set_state(w.phi0)
+    s.step(2)
+    s.sync()
+    s.close()
