@@ -89,7 +89,7 @@ __global__ __launch_bounds__(NT) void k_bhydro(BatchPtrs B, const BatchDomain *_
         if (it + r.stride < r.end) nxt = items[it + r.stride];  // next record loads during this item
         const BatchDomain d = dom[dt.x];
         const DomPtrs P = domain_ptrs(B, d, cur);
-        hydro_node(d.g, d.p, tile_node(d.g, d.t, dt.y), P.fin, P.fout, P.phi_cur, P.nbr, P.u, B.flag);
+        hydro_node<false>(d.g, d.p, tile_node(d.g, d.t, dt.y), P.fin, P.fout, P.phi_cur, P.nbr, P.u, B.flag);
     }
 }
 
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(NT) void k_bhydro1(BatchPtrs B, const BatchDomain *
     const uint2 dt = items[xcd_tile(blockIdx.x, nitems)];
     const BatchDomain d = dom[dt.x];
     const DomPtrs P = domain_ptrs(B, d, cur);
-    hydro_node(d.g, d.p, tile_node(d.g, d.t, dt.y), P.fin, P.fout, P.phi_cur, P.nbr, P.u, B.flag);
+    hydro_node<false>(d.g, d.p, tile_node(d.g, d.t, dt.y), P.fin, P.fout, P.phi_cur, P.nbr, P.u, B.flag);
 }
 
 template <int BX, int BY>
@@ -141,22 +141,48 @@ __global__ __launch_bounds__(256) void k_bvol_finalize(BatchPtrs B, const BatchD
     }
 }
 
-// phi <- phi* + lambda_k chi(phi*) on fluid nodes (Eq. (53)), one thread per node
-// of the concatenated arrays.  The block's first domain comes from a host-built
-// table; a node past its end belongs to a following domain (a block straddles
-// domains only at their boundaries).
+// phi <- phi* + lambda_k chi(phi*) on fluid nodes (Eq. (53)), four consecutive
+// nodes of the concatenated arrays per thread (VEC: 16-byte phi and 4-byte
+// mask loads).  The domain of the first node comes from a host-built table of
+// the domain of each 256-node block; a later node past the domain's end
+// belongs to a following domain (quads straddle domains only at their
+// boundaries).  The population and mask loads do not depend on the lookup.
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_bvol_apply(BatchPtrs B, const BatchDomain *__restrict__ dom, int cur_next)
 {
-    const uint32_t n = blockIdx.x * 256u + threadIdx.x;
-    if (n >= B.ntot || B.solid[n]) return;
-    uint32_t lo = B.blk_dom[blockIdx.x];
-    while (n >= B.dom_start[lo + 1]) ++lo;
+    const uint32_t n0 = 4u * (blockIdx.x * 256u + threadIdx.x);
+    if (n0 >= B.ntot) return;
     float *phi = cur_next ? B.phi[1] : B.phi[0];
-    const float v = phi[n];
-    const float eps = dom[lo].p.eps_phi;
-    if (v > eps && v < 1.0f - eps) {
-        const double lam = B.scal[8u * lo + 1];
-        phi[n] = (float)((double)v + lam * ((double)v * (1.0 - (double)v)));
+    uint8_t s[4];
+    float v[4];
+    const int cnt = (int)min(4u, B.ntot - n0);
+    if (VEC && cnt == 4) {
+        const uchar4 s4 = *reinterpret_cast<const uchar4 *>(B.solid + n0);
+        const float4 v4 = *reinterpret_cast<const float4 *>(phi + n0);
+        s[0] = s4.x, s[1] = s4.y, s[2] = s4.z, s[3] = s4.w;
+        v[0] = v4.x, v[1] = v4.y, v[2] = v4.z, v[3] = v4.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            s[k] = k < cnt ? B.solid[n0 + k] : (uint8_t)1;
+            v[k] = k < cnt ? phi[n0 + k] : 0.f;
+        }
+    }
+    uint32_t lo = B.blk_dom[n0 >> 8];
+    uint32_t end = B.dom_start[lo + 1];
+    while (n0 >= end) end = B.dom_start[++lo + 1];
+    float eps = dom[lo].p.eps_phi;
+    double lam = B.scal[8u * lo + 1];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t n = n0 + (uint32_t)k;
+        if (k > 0 && k < cnt && n >= end) {
+            while (n >= end) end = B.dom_start[++lo + 1];
+            eps = dom[lo].p.eps_phi;
+            lam = B.scal[8u * lo + 1];
+        }
+        if (!s[k] && v[k] > eps && v[k] < 1.0f - eps)
+            phi[n] = (float)((double)v[k] + lam * ((double)v[k] * (1.0 - (double)v[k])));
     }
 }
 
@@ -222,7 +248,12 @@ hipError_t launch_bvolume(const BatchPtrs &B, int nt, const uint2 *items, uint32
     k_bvol_finalize<<<B.ndom, 256, 0, s>>>(B, B.dom);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !B.ntot) return e;
-    k_bvol_apply<<<(B.ntot + 255u) / 256u, 256, 0, s>>>(B, B.dom, cur_next);
+    const unsigned nb = ((B.ntot + 3u) / 4u + 255u) / 256u;
+    const float *phi = cur_next ? B.phi[1] : B.phi[0];
+    if ((((uintptr_t)B.solid | (uintptr_t)phi) & 15u) == 0)
+        k_bvol_apply<true><<<nb, 256, 0, s>>>(B, B.dom, cur_next);
+    else
+        k_bvol_apply<false><<<nb, 256, 0, s>>>(B, B.dom, cur_next);
     return hipGetLastError();
 }
 

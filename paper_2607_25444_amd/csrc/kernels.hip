@@ -32,13 +32,13 @@ __global__ __launch_bounds__(256) void k_ghost(Grid g, DevParams p, const int32_
     if (k < nwall) ghost_node(g, p, k, widx, wq, wn, theta, phi_cur, phi_old, nbr, a);
 }
 
-template <int NT>
+template <int NT, bool NTL>
 __global__ __launch_bounds__(NT) void k_hydro(Grid g, Tiling t, DevParams p, const float *__restrict__ fin,
                                               float *__restrict__ fout, const float *__restrict__ phi,
                                               const uint32_t *__restrict__ nbr, float *__restrict__ u,
                                               uint32_t *__restrict__ flag)
 {
-    hydro_node(g, p, tile_node(g, t, xcd_tile(blockIdx.x, t.ntiles)), fin, fout, phi, nbr, u, flag);
+    hydro_node<NTL>(g, p, tile_node(g, t, xcd_tile(blockIdx.x, t.ntiles)), fin, fout, phi, nbr, u, flag);
 }
 
 template <int BX, int BY>
@@ -73,16 +73,31 @@ __global__ __launch_bounds__(1024) void k_vol_finalize(const double2 *__restrict
     }
 }
 
-// phi^{n+1} = phi* + lambda chi(phi*) on fluid nodes (Eq. (53)).
+// phi^{n+1} = phi* + lambda chi(phi*) on fluid nodes (Eq. (53)).  Four
+// consecutive nodes per thread; VEC: one 16-byte phi load and one 4-byte mask
+// load (both buffers 16-byte aligned).  Only interface nodes are stored.
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_vol_apply(uint32_t N, const uint8_t *__restrict__ solid,
                                                    float *__restrict__ phi, const double *__restrict__ scal,
                                                    float eps_phi)
 {
-    const uint32_t n = blockIdx.x * 256u + threadIdx.x;
-    if (n >= N || solid[n]) return;
+    const uint32_t n0 = 4u * (blockIdx.x * 256u + threadIdx.x);
+    if (n0 >= N) return;
     const double lam = scal[1];
-    const float v = phi[n];
-    if (v > eps_phi && v < 1.0f - eps_phi) phi[n] = (float)((double)v + lam * ((double)v * (1.0 - (double)v)));
+    auto one = [&](uint32_t n, uint8_t s, float v) {
+        if (!s && v > eps_phi && v < 1.0f - eps_phi)
+            phi[n] = (float)((double)v + lam * ((double)v * (1.0 - (double)v)));
+    };
+    if (VEC && n0 + 4u <= N) {
+        const uchar4 s = *reinterpret_cast<const uchar4 *>(solid + n0);
+        const float4 v = *reinterpret_cast<const float4 *>(phi + n0);
+        one(n0, s.x, v.x);
+        one(n0 + 1u, s.y, v.y);
+        one(n0 + 2u, s.z, v.z);
+        one(n0 + 3u, s.w, v.w);
+    } else {
+        for (uint32_t n = n0; n < min(n0 + 4u, N); ++n) one(n, solid[n], phi[n]);
+    }
 }
 
 // Out-of-place correction used when the forward sweep is recorded: phi* stays
@@ -200,18 +215,22 @@ hipError_t launch_hydro(const Grid &g, const Tiling &t, const DevParams &p, cons
                         hipStream_t s)
 {
     const int nt = t.bx * t.by * t.bz;
+    // non-temporal population loads when a workgroup spans whole rows (see hydro_node)
+    const bool ntl = t.bx >= g.nx;
+#define CAC_HYDRO(NT_)                                                                                                \
+    if (ntl)                                                                                                          \
+        k_hydro<NT_, true><<<t.ntiles, NT_, 0, s>>>(g, t, p, F.f[fcur], F.f[fcur ^ 1], F.phi[pcur], F.nbr, F.u,       \
+                                                    F.flag);                                                          \
+    else                                                                                                              \
+        k_hydro<NT_, false><<<t.ntiles, NT_, 0, s>>>(g, t, p, F.f[fcur], F.f[fcur ^ 1], F.phi[pcur], F.nbr, F.u,      \
+                                                     F.flag);
     switch (nt) {
-    case 128:
-        k_hydro<128><<<t.ntiles, 128, 0, s>>>(g, t, p, F.f[fcur], F.f[fcur ^ 1], F.phi[pcur], F.nbr, F.u, F.flag);
-        break;
-    case 256:
-        k_hydro<256><<<t.ntiles, 256, 0, s>>>(g, t, p, F.f[fcur], F.f[fcur ^ 1], F.phi[pcur], F.nbr, F.u, F.flag);
-        break;
-    case 512:
-        k_hydro<512><<<t.ntiles, 512, 0, s>>>(g, t, p, F.f[fcur], F.f[fcur ^ 1], F.phi[pcur], F.nbr, F.u, F.flag);
-        break;
+    case 128: CAC_HYDRO(128) break;
+    case 256: CAC_HYDRO(256) break;
+    case 512: CAC_HYDRO(512) break;
     default: return hipErrorInvalidValue;
     }
+#undef CAC_HYDRO
     return hipGetLastError();
 }
 
@@ -296,7 +315,11 @@ hipError_t launch_volume(const Grid &g, const Tiling &t, const DevParams &p, con
     k_vol_finalize<<<1, 1024, 0, s>>>(F.partial, phase_tiles(g, t), F.scal, p.volume_correction);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_vol_apply<<<blocks_for(g.N, 256), 256, 0, s>>>(g.N, F.solid, F.phi[pnext], F.scal, p.eps_phi);
+    const unsigned nb = blocks_for(blocks_for(g.N, 4), 256);
+    if ((((uintptr_t)F.solid | (uintptr_t)F.phi[pnext]) & 15u) == 0)
+        k_vol_apply<true><<<nb, 256, 0, s>>>(g.N, F.solid, F.phi[pnext], F.scal, p.eps_phi);
+    else
+        k_vol_apply<false><<<nb, 256, 0, s>>>(g.N, F.solid, F.phi[pnext], F.scal, p.eps_phi);
     return hipGetLastError();
 }
 

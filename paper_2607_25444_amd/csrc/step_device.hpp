@@ -229,19 +229,26 @@ __host__ __device__ __forceinline__ float fast_rcp(float x)
 
 // Pull of the populations that stream into node n (Sec. II A): f_i(x) =
 // f*_i(x - c_i), or f*_opp(i)(x) when x - c_i is solid (halfway bounce-back),
-// taken pair by pair (i, opp(i) = i + 1).  Non-temporal: each population is
-// read once per step.
+// taken pair by pair (i, opp(i) = i + 1).  NTL: non-temporal loads (each
+// population is read once per step).
+template <bool NTL>
 __device__ __forceinline__ void pull_populations(const Grid &g, const Offs &o, uint32_t n, uint32_t m,
                                                  const float *__restrict__ fin, float (&f)[27])
 {
     const uint32_t N = g.N;
-    f[0] = __builtin_nontemporal_load(&fin[n]);
+    auto ld = [&](uint32_t k) {
+        if constexpr (NTL)
+            return __builtin_nontemporal_load(&fin[k]);
+        else
+            return fin[k];
+    };
+    f[0] = ld(n);
     static_for<13>([&](auto P) {
         constexpr int i = 2 * P + 1;
         const uint32_t src_i = at<Lat::cx[i + 1], Lat::cy[i + 1], Lat::cz[i + 1]>(o);
-        f[i] = __builtin_nontemporal_load(&fin[((m >> (i + 1)) & 1u) ? (uint32_t)(i + 1) * N + n : (uint32_t)i * N + src_i]);
+        f[i] = ld(((m >> (i + 1)) & 1u) ? (uint32_t)(i + 1) * N + n : (uint32_t)i * N + src_i);
         const uint32_t src_o = at<Lat::cx[i], Lat::cy[i], Lat::cz[i]>(o);
-        f[i + 1] = __builtin_nontemporal_load(&fin[((m >> i) & 1u) ? (uint32_t)i * N + n : (uint32_t)(i + 1) * N + src_o]);
+        f[i + 1] = ld(((m >> i) & 1u) ? (uint32_t)i * N + n : (uint32_t)(i + 1) * N + src_o);
     });
 }
 
@@ -287,9 +294,16 @@ __host__ __device__ __forceinline__ void pair_moments(const float (&f)[27], floa
 //     C2 = uu + (ua + au)/2 + (1 - omega) A2,  C3 = uuu + (1 - omega) S(u A2),
 //     A2 = P - p*/3 I - uu + (ua + au)/2  (second moment of f - f^eq + S/2).
 //   Writes f* and u.
-//   Populations are read and written with non-temporal hints: each is touched
-//   once per step and the 27-plane sets are far larger than the caches, so
-//   they should not evict phi, u and the masks, which the stencils re-read.
+//   Populations are written with non-temporal hints: each is touched once per
+//   step and the 27-plane sets are far larger than the caches, so they should
+//   not evict phi, u and the masks, which the stencils re-read.  NTL = true
+//   reads them with the same hint; that pays when a workgroup covers whole
+//   rows of a large lattice (the single-lattice kernel), whose y and z
+//   neighbour rows are pulled by workgroups running at the same time.  The
+//   batched kernel's smaller tiles re-read neighbour rows later, from L2, and
+//   run faster with ordinary loads (NTL = false; about 10% on the 64-domain
+//   batch).
+template <bool NTL>
 __device__ __forceinline__ void hydro_node(const Grid &g, const DevParams &p, const Node &nd,
                                            const float *__restrict__ fin, float *__restrict__ fout,
                                            const float *__restrict__ phi, const uint32_t *__restrict__ nbr,
@@ -308,7 +322,7 @@ __device__ __forceinline__ void hydro_node(const Grid &g, const DevParams &p, co
         s[kk] = phi[at<kk % 3 - 1, (kk / 3) % 3 - 1, kk / 9 - 1>(o)];
     });
     float f[27];
-    pull_populations(g, o, n, m, fin, f);
+    pull_populations<NTL>(g, o, n, m, fin, f);
 
     float gx, gy, gz, lap;
     stencil_grad_lap(s, gx, gy, gz, lap);
