@@ -459,11 +459,11 @@ __device__ __forceinline__ void block_sum2(double &x, double &y)
 
 // CAC update (Eq. (28)) as a 2.5-D stencil: a workgroup owns a BX x BY
 // column tile and marches up a chunk of ZC planes.  LDS holds a ring of five
-// phi planes (z-2..z+2, halo 2 in x and y) and a ring of three planes of the
-// compressive flux a = phi(1-phi) grad/|grad| (z-1..z+1, halo 1) together
-// with the solid flags.  At each plane: load phi(z+2), build a(z+1) from the
-// isotropic gradient (Eq. (22), normal of Eq. (25)), then update the nodes of
-// plane z:
+// phi planes (z-2..z+2, halo 2 in x and y), a ring of three planes of the
+// compressive flux a = phi(1-phi) grad/|grad| (z-1..z+1, halo 1) and a ring
+// of four planes of solid flags (z-1..z+2).  At each plane: store phi(z+2)
+// and the flags of z+1, build a(z+1) from the isotropic gradient (Eq. (22),
+// normal of Eq. (25)), then update the nodes of plane z:
 //   phi* = phi - div(F_a) + D lap(phi) - kappa div_iso(a)
 // with MUSCL-minmod face fluxes (Eqs. (29)-(34)), zero on faces touching a
 // solid node, and div_iso with the weights w_i/c_s^2.  On solid nodes a is
@@ -474,6 +474,21 @@ __host__ __device__ __forceinline__ int wrapc(int v, int n)
 {
     v %= n;
     return v < 0 ? v + n : v;
+}
+
+// Element at a byte offset from a base pointer.  In the phase kernel the base
+// is a plane (uniform across the workgroup, held in scalar registers) and the
+// offset a 32-bit per-thread constant, so each access is one load or store
+// with a scalar base and no 64-bit address arithmetic.
+template <class T>
+__device__ __forceinline__ T &at_byte(T *base, uint32_t off)
+{
+    return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off);
+}
+template <class T>
+__device__ __forceinline__ const T &at_byte(const T *base, uint32_t off)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
 }
 
 // Per-plane partial sums of the tensor-product stencils on a 3x3 plane patch
@@ -536,10 +551,11 @@ __device__ __forceinline__ void phase_tile(const Grid &g, const PhaseTiling &pt,
     constexpr int HX = BX + 4, HY = BY + 4;  // phi plane, halo 2
     constexpr int AX = BX + 2, AY = BY + 2;  // flux / flag plane, halo 1
     constexpr int PF = (HX * HY + NT - 1) / NT;  // phi values per thread per plane
-    constexpr int PA = (AX * AY + NT - 1) / NT;  // flux points per thread per plane
+    constexpr int NRING = 2 * (AX + AY) - 4;    // halo-1 points outside the tile
+    constexpr int PA = 1 + (NRING + NT - 1) / NT;  // flux points per thread per plane
     __shared__ float sphi[5][HY][HX];
     __shared__ float sa[3][3][AY][AX];
-    __shared__ uint8_t ssol[3][AY][AX];
+    __shared__ uint8_t ssol[4][AY][AX];
 
     const int tcx = (int)(tile % (uint32_t)pt.ntx);
     const int tcy = (int)((tile / (uint32_t)pt.ntx) % (uint32_t)pt.nty);
@@ -554,6 +570,7 @@ __device__ __forceinline__ void phase_tile(const Grid &g, const PhaseTiling &pt,
 
     auto pslot = [&](int zz) { return (zz - z0 + 10) % 5; };
     auto aslot = [&](int zz) { return (zz - z0 + 3) % 3; };
+    auto sslot = [&](int zz) { return (zz - z0 + 4) & 3; };
     // plane offset with periodic wrap; the planes visited lie within a few of [0, nz),
     // so the modulo (a long integer division) is taken only off that range
     auto zoff = [&](int zz) {
@@ -561,27 +578,45 @@ __device__ __forceinline__ void phase_tile(const Grid &g, const PhaseTiling &pt,
         return (uint32_t)w * g.nxny;
     };
 
-    // this thread's share of the halo planes: global in-plane offset and LDS position
+    // this thread's share of the halo planes: in-plane offset (bytes for phi,
+    // nodes for the flags) and LDS position
     uint32_t pxy[PF], axy[PA];
     int apos[PA];
 #pragma unroll
     for (int r = 0; r < PF; ++r) {
         const int k = tid + r * NT;
         const int hx = k % HX, hy = k / HX;
-        pxy[r] = k < HX * HY ? (uint32_t)wrapc(x0 - 2 + hx, g.nx) + (uint32_t)wrapc(y0 - 2 + hy, g.ny) * (uint32_t)g.nx : 0u;
+        pxy[r] = k < HX * HY ? 4u * ((uint32_t)wrapc(x0 - 2 + hx, g.nx) + (uint32_t)wrapc(y0 - 2 + hy, g.ny) * (uint32_t)g.nx) : 0u;
     }
+    // flux points (and solid flags) of this thread in the halo-1 plane: r = 0 is
+    // its own column, so the plane sums build_a forms there serve the column's
+    // update too; r >= 1 walk the ring around the tile (rows 0 and AY-1, then
+    // columns 0 and AX-1)
 #pragma unroll
     for (int r = 0; r < PA; ++r) {
-        const int k = tid + r * NT;
-        const int ax = k % AX, ay = k / AX;
-        axy[r] = k < AX * AY ? (uint32_t)wrapc(x0 - 1 + ax, g.nx) + (uint32_t)wrapc(y0 - 1 + ay, g.ny) * (uint32_t)g.nx : 0u;
-        apos[r] = k < AX * AY ? ay * AX + ax : -1;
+        int ax = lx + 1, ay = ly + 1;
+        bool ok = true;
+        if (r > 0) {
+            const int j = tid + (r - 1) * NT;
+            ok = j < NRING;
+            if (j < 2 * AX) {
+                ax = j % AX;
+                ay = j < AX ? 0 : AY - 1;
+            } else {
+                const int k = j - 2 * AX;
+                ax = k < AY - 2 ? 0 : AX - 1;
+                ay = 1 + k % (AY - 2);
+            }
+        }
+        axy[r] = ok ? (uint32_t)wrapc(x0 - 1 + ax, g.nx) + (uint32_t)wrapc(y0 - 1 + ay, g.ny) * (uint32_t)g.nx : 0u;
+        apos[r] = ok ? ay * AX + ax : -1;
     }
+    auto aval = [&](int r) { return r == 0 || apos[r] >= 0; };
     auto fetch_phi = [&](int zz, float (&v)[PF]) {
         const uint32_t zo = zoff(zz);
 #pragma unroll
         for (int r = 0; r < PF; ++r)
-            if (tid + r * NT < HX * HY) v[r] = phi[pxy[r] + zo];
+            if (tid + r * NT < HX * HY) v[r] = at_byte(phi + zo, pxy[r]);
     };
     auto store_phi = [&](int zz, const float (&v)[PF]) {
         float *dst = &sphi[pslot(zz)][0][0];
@@ -593,13 +628,13 @@ __device__ __forceinline__ void phase_tile(const Grid &g, const PhaseTiling &pt,
         const uint32_t zo = zoff(zz);
 #pragma unroll
         for (int r = 0; r < PA; ++r)
-            if (apos[r] >= 0) v[r] = solid[axy[r] + zo];
+            if (aval(r)) v[r] = at_byte(solid + zo, axy[r]);
     };
     auto store_sol = [&](int zz, const uint8_t (&v)[PA]) {
-        uint8_t *dst = &ssol[aslot(zz)][0][0];
+        uint8_t *dst = &ssol[sslot(zz)][0][0];
 #pragma unroll
         for (int r = 0; r < PA; ++r)
-            if (apos[r] >= 0) dst[apos[r]] = v[r];
+            if (aval(r)) dst[apos[r]] = v[r];
     };
     // 3x3 patch of phi plane zz centred on halo-1 position (ax, ay) (= halo-2 position + 1)
     auto patch = [&](int zz, int ax, int ay, float (&v)[9]) {
@@ -613,7 +648,7 @@ __device__ __forceinline__ void phase_tile(const Grid &g, const PhaseTiling &pt,
     auto flux_points_sums = [&](int zz, PlaneSums (&out)[PA]) {
 #pragma unroll
         for (int r = 0; r < PA; ++r) {
-            if (apos[r] < 0) continue;
+            if (!aval(r)) continue;
             float v[9];
             patch(zz, apos[r] % AX, apos[r] / AX, v);
             out[r] = plane_sums(v);
@@ -627,10 +662,10 @@ __device__ __forceinline__ void phase_tile(const Grid &g, const PhaseTiling &pt,
         flux_points_sums(zz + 1, nxt);
 #pragma unroll
         for (int r = 0; r < PA; ++r) {
-            if (apos[r] < 0) continue;
+            if (!aval(r)) continue;
             const int pos = apos[r];
             float cx = 0.f, cy = 0.f, cz = 0.f;
-            if ((&ssol[sl][0][0])[pos]) {
+            if ((&ssol[sslot(zz)][0][0])[pos]) {
                 if (p.wall_compression) {
                     const uint32_t id = axy[r] + zo;
                     cx = aw[id];
@@ -658,25 +693,26 @@ __device__ __forceinline__ void phase_tile(const Grid &g, const PhaseTiling &pt,
         }
     };
 
-    // velocities this node's fluxes need on plane zz
-    const uint32_t cxy = col_in ? (uint32_t)x + (uint32_t)y * (uint32_t)g.nx : 0u;
-    const uint32_t xm = col_in ? (uint32_t)wrapc(x - 1, g.nx) + (uint32_t)y * (uint32_t)g.nx : 0u;
-    const uint32_t xp = col_in ? (uint32_t)wrapc(x + 1, g.nx) + (uint32_t)y * (uint32_t)g.nx : 0u;
-    const uint32_t ym = col_in ? (uint32_t)x + (uint32_t)wrapc(y - 1, g.ny) * (uint32_t)g.nx : 0u;
-    const uint32_t yp = col_in ? (uint32_t)x + (uint32_t)wrapc(y + 1, g.ny) * (uint32_t)g.nx : 0u;
+    // velocities this node's fluxes need on plane zz (in-plane byte offsets)
+    const uint32_t cxy = col_in ? 4u * ((uint32_t)x + (uint32_t)y * (uint32_t)g.nx) : 0u;
+    const uint32_t xm = col_in ? 4u * ((uint32_t)wrapc(x - 1, g.nx) + (uint32_t)y * (uint32_t)g.nx) : 0u;
+    const uint32_t xp = col_in ? 4u * ((uint32_t)wrapc(x + 1, g.nx) + (uint32_t)y * (uint32_t)g.nx) : 0u;
+    const uint32_t ym = col_in ? 4u * ((uint32_t)x + (uint32_t)wrapc(y - 1, g.ny) * (uint32_t)g.nx) : 0u;
+    const uint32_t yp = col_in ? 4u * ((uint32_t)x + (uint32_t)wrapc(y + 1, g.ny) * (uint32_t)g.nx) : 0u;
     struct UPlane {
         float xm, xc, xp, ym, yc, yp, zn;  // zn: u_z one plane up
     };
     auto fetch_u = [&](int zz, UPlane &v) {
         if (!col_in) return;
         const uint32_t zo = zoff(zz);
-        v.xm = u[xm + zo];
-        v.xc = u[cxy + zo];
-        v.xp = u[xp + zo];
-        v.ym = u[N + ym + zo];
-        v.yc = u[N + cxy + zo];
-        v.yp = u[N + yp + zo];
-        v.zn = u[2u * N + cxy + zoff(zz + 1)];
+        const float *ux = u + zo, *uy = u + N + zo, *uz = u + 2u * N + zoff(zz + 1);
+        v.xm = at_byte(ux, xm);
+        v.xc = at_byte(ux, cxy);
+        v.xp = at_byte(ux, xp);
+        v.ym = at_byte(uy, ym);
+        v.yc = at_byte(uy, cxy);
+        v.yp = at_byte(uy, yp);
+        v.zn = at_byte(uz, cxy);
     };
 
     const int hx = lx + 2, hy = ly + 2, ax = lx + 1, ay = ly + 1;
@@ -740,14 +776,33 @@ __device__ __forceinline__ void phase_tile(const Grid &g, const PhaseTiling &pt,
     fetch_sol(z0 + 1, nsol);
     fetch_u(z0, uc);
     if (col_in) {
-        uzm = u[2u * N + cxy + zoff(z0 - 1)];
-        uzc = u[2u * N + cxy + zoff(z0)];
+        uzm = at_byte(u + 2u * N + zoff(z0 - 1), cxy);
+        uzc = at_byte(u + 2u * N + zoff(z0), cxy);
     }
     uzp = uc.zn;
+    // z axis of the advective flux, rolled along the column: the slope at the
+    // node (zsc), phi(z+1) - phi(z) (zd2) and the face flux at z-1/2 before the
+    // solid test (zfm) carry over from plane z-1, where they were the upper
+    // slope, the upper difference and the flux at its z+1/2 face
+    float zsc, zd2, zfm;
+    {
+        const float q3 = sphi[pslot(z0 + 1)][hy][hx];
+        const float d0 = c_m - c_m2, d1 = c_c - c_m, d2 = q3 - c_c;
+        const float sm = minmod2(d0, d1);
+        zsc = minmod2(d1, d2);
+        zd2 = d2;
+        const float uf = 0.5f * (uzm + uzc);
+        zfm = uf * (uf >= 0.0f ? c_m + 0.5f * sm : c_c - 0.5f * zsc);
+    }
 
     double sphis = 0.0, schi = 0.0;
-    for (int z = z0; z < z1; ++z) {
-        __syncthreads();  // the previous plane is done with the slots overwritten below
+    // one plane of the march; called twice per loop trip (the unrolled form
+    // keeps the rolled column state in place instead of copying it)
+    auto plane = [&](const int z) __attribute__((always_inline)) {
+        // Two barriers per plane.  The stores below may run while slower waves
+        // still update plane z-1, which reads phi planes z-1..z+1, flux plane z
+        // and flag planes z-2..z: the slots written here (phi z+2, flags z+1)
+        // are none of those, with rings of five and four.
         store_phi(z + 2, nphi);
         store_sol(z + 1, nsol);
         if (z + 1 < z1) {  // prefetch for the next plane; lands while this one computes
@@ -758,28 +813,33 @@ __device__ __forceinline__ void phase_tile(const Grid &g, const PhaseTiling &pt,
         __syncthreads();
         build_a(z + 1);
         __syncthreads();
-        // new column sums of plane z+1 (phi) and flux plane z+1
-        float v[9];
-        col_patch(z + 1, v);
-        const PlaneSums sp = plane_sums(v);
+        // new column sums of plane z+1 (phi: this thread's own flux point,
+        // just rolled into bprev[0]) and flux plane z+1
+        const PlaneSums sp = bprev[0];
+        const float *p1 = &sphi[pslot(z + 1)][0][0];
+        const int h0 = hy * HX + hx;
+        const float nx_m = p1[h0 - 1], nx_p = p1[h0 + 1], ny_m = p1[h0 - HX], ny_p = p1[h0 + HX];
         float X_p, Y_p, Z_p;
         flux_sums(z + 1, X_p, Y_p, Z_p);
-        const int sa_c = aslot(z);
-        const uint8_t *fl = &ssol[sa_c][0][0];
+        // z flux at z+1/2 (Eqs. (30)-(34)), for every column so that it rolls
+        const float c_p2 = sphi[pslot(z + 2)][hy][hx];
+        const float zd3 = c_p2 - sp.c;
+        const float zsp = minmod2(zd2, zd3);
+        const float ufp = 0.5f * (uzc + uzp);
+        const float zfp = ufp * (ufp >= 0.0f ? c_c + 0.5f * zsc : sp.c - 0.5f * zsp);
+        const uint8_t *fl = &ssol[sslot(z)][0][0];
         const int c0 = ay * AX + ax;
         if (col_in && !fl[c0]) {
             const float ph = c_c;
             const float lap = (tq_m + 4.0f * tq_c + sp.tq + 36.0f * ((c_m - ph) + (sp.c - ph))) * (1.0f / 36.0f);
             const float *p0 = &sphi[pslot(z)][0][0];
-            const int h0 = hy * HX + hx;
-            const float c_p2 = sphi[pslot(z + 2)][hy][hx];
             float div_a = muscl_axis(p0[h0 - 2], cr_xm, ph, cr_xp, p0[h0 + 2], uc.xm, uc.xc, uc.xp, !fl[c0 - 1], !fl[c0 + 1]);
             div_a += muscl_axis(p0[h0 - 2 * HX], cr_ym, ph, cr_yp, p0[h0 + 2 * HX], uc.ym, uc.yc, uc.yp, !fl[c0 - AX],
                                 !fl[c0 + AX]);
-            div_a += muscl_axis(c_m2, c_m, ph, sp.c, c_p2, uzm, uzc, uzp, !ssol[aslot(z - 1)][ay][ax], !ssol[aslot(z + 1)][ay][ax]);
+            div_a += (!ssol[sslot(z + 1)][ay][ax] ? zfp : 0.0f) - (!ssol[sslot(z - 1)][ay][ax] ? zfm : 0.0f);
             const float div_c = (X_m + 4.0f * X_c + X_p + Y_m + 4.0f * Y_c + Y_p + Z_p - Z_m) * (1.0f / 72.0f);
             const float ps = ph - div_a + p.D * lap - p.kappa * div_c;
-            phi_out[cxy + (uint32_t)z * g.nxny] = ps;
+            at_byte(phi_out + (uint32_t)z * g.nxny, cxy) = ps;
             if (!isfinite(ps)) flag[0] = 1u;
             sphis += (double)ps;
             if (ps > p.eps_phi && ps < 1.0f - p.eps_phi) schi += (double)ps * (1.0 - (double)ps);
@@ -787,13 +847,15 @@ __device__ __forceinline__ void phase_tile(const Grid &g, const PhaseTiling &pt,
         // roll the column state to plane z+1
         tq_m = tq_c;
         tq_c = sp.tq;
-        c_m2 = c_m;
         c_m = c_c;
         c_c = sp.c;
-        cr_xm = v[3];
-        cr_xp = v[5];
-        cr_ym = v[1];
-        cr_yp = v[7];
+        cr_xm = nx_m;
+        cr_xp = nx_p;
+        cr_ym = ny_m;
+        cr_yp = ny_p;
+        zsc = zsp;
+        zd2 = zd3;
+        zfm = zfp;
         X_m = X_c;
         X_c = X_p;
         Y_m = Y_c;
@@ -801,10 +863,15 @@ __device__ __forceinline__ void phase_tile(const Grid &g, const PhaseTiling &pt,
         Z_m = Z_c;
         Z_c = Z_p;
         uc = un;
-        uzm = uzc;
         uzc = uzp;
         uzp = un.zn;
+    };
+    int z = z0;
+    for (; z + 1 < z1; z += 2) {
+        plane(z);
+        plane(z + 1);
     }
+    if (z < z1) plane(z);
     block_sum2<NT>(sphis, schi);
     if (tid == 0) *partial_out = make_double2(sphis, schi);
 }
