@@ -121,6 +121,20 @@ __global__ __launch_bounds__(BX *BY) void k_bphase(BatchPtrs B, const BatchDomai
     }
 }
 
+// One workgroup per item (the schedule's grid multiplier 0).  Without the item
+// loop of k_bphase the kernel keeps the register budget of the single-lattice
+// phase kernel (about 120 VGPRs instead of 170-200), so twice the waves fit.
+template <int BX, int BY>
+__global__ __launch_bounds__(BX *BY) void k_bphase1(BatchPtrs B, const BatchDomain *__restrict__ dom,
+                                                    const uint2 *__restrict__ items, uint32_t nitems, int cur)
+{
+    const uint2 dt = items[xcd_tile(blockIdx.x, nitems)];
+    const BatchDomain d = dom[dt.x];
+    const DomPtrs P = domain_ptrs(B, d, cur);
+    phase_tile<BX, BY>(d.g, d.pt, d.p, dt.y, P.phi_cur, P.phi_oth, P.u, P.a, P.solid, B.partial + d.p_item0 + dt.y,
+                       B.flag);
+}
+
 // One workgroup per domain: lambda_k from its tile partials in a fixed order.
 __global__ __launch_bounds__(256) void k_bvol_finalize(BatchPtrs B, const BatchDomain *__restrict__ dom)
 {
@@ -225,7 +239,10 @@ hipError_t launch_bphase(const BatchPtrs &B, int code, const uint2 *items, uint3
     phase_shape_of(code, bx, by);
 #define CAC_BPHASE(BX_, BY_)                                                        \
     if (bx == BX_ && by == BY_) {                                                   \
-        k_bphase<BX_, BY_><<<grid, BX_ * BY_, 0, s>>>(B, B.dom, items, nitems, cur); \
+        if (grid >= nitems)                                                         \
+            k_bphase1<BX_, BY_><<<nitems, BX_ * BY_, 0, s>>>(B, B.dom, items, nitems, cur); \
+        else                                                                        \
+            k_bphase<BX_, BY_><<<grid, BX_ * BY_, 0, s>>>(B, B.dom, items, nitems, cur); \
         return hipGetLastError();                                                   \
     }
     CAC_BPHASE(64, 8)

@@ -146,9 +146,9 @@ cac_status apply_schedule(cac_batch *b, const Schedule &s)
         d.t = make_tiling(d.g, tx, ty, tz);
         d.t.phase = s.phase;
         d.pt = phase_tiling(d.g, pbx, pby);
-        // the batch supplies the parallelism: chunks of 16 planes keep the
-        // per-chunk prologue of the phase kernel small
-        d.pt.zc = std::min(16, d.g.nz);
+        // the batch supplies the parallelism: whole chunks of up to 32 planes
+        // pay the phase kernel's per-chunk prologue least often
+        d.pt.zc = std::min(32, d.g.nz);
         d.pt.nzc = (d.g.nz + d.pt.zc - 1) / d.pt.zc;
         d.pt.ntiles = (uint32_t)d.pt.ntx * (uint32_t)d.pt.nty * (uint32_t)d.pt.nzc;
         d.p_item0 = p0;
