@@ -77,9 +77,9 @@ def cpu_baseline(w, steps):
                        f"{dt:.1f} s wall")
 
 
-def copy_probe(torch, nbytes=1 << 30, reps=20):
+def copy_probe(torch, nbytes=1 << 30, reps=20, quiet=False):
     """Elementwise copy of nbytes (read nbytes, write nbytes) with torch's
-    streaming kernel; prints the achieved GB/s as JSON."""
+    streaming kernel; returns (and unless quiet prints as JSON) the GB/s."""
     n = nbytes // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
@@ -92,8 +92,12 @@ def copy_probe(torch, nbytes=1 << 30, reps=20):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "ms": round(ms, 4),
-                      "GBs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}), flush=True)
+    gbs = 2 * nbytes / (ms * 1e-3) / 1e9
+    if not quiet:
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "ms": round(ms, 4),
+                          "GBs": round(gbs, 1)}), flush=True)
+    del src, dst
+    return gbs
 
 
 def bench_batch(torch, capi, W, steps, warmup, seed, singles=True, tune_cache=None):
@@ -295,6 +299,14 @@ def main():
     M1 = sim.volume()
     log(f"[bench] kernel ms/step W={kavg[0]:.4f} H={kavg[1]:.4f} P={kavg[2]:.4f} V={kavg[3]:.4f}; "
         f"hydro {achieved:.0f} GB/s; volume drift {(M1 - M0) / M0:.2e}")
+    # achievable ceilings, measured live after the timed region: the
+    # collide-stream's memory access pattern without its arithmetic (27-plane
+    # pull copy, 216 B per node over all nodes; leaves the handle without a
+    # state) and a plain 1 GiB streaming copy
+    pull_ms = sim.pull_copy_probe(20)
+    pull_gbs = w.N * 216 / (pull_ms * 1e-3) / 1e9
+    copy_gbs = copy_probe(torch, reps=10, quiet=True)
+    log(f"[bench] ceilings: pull copy {pull_gbs:.0f} GB/s ({pull_ms:.4f} ms), plain copy {copy_gbs:.0f} GB/s")
 
     rec = {
         "metric": METRIC,
@@ -338,6 +350,14 @@ def main():
             "bytes_per_lu": STEP_BYTES_PER_LU,
             "mlups_all_nodes": round(w.N * args.steps / (ms * 1e-3) / 1e6, 2),
             "volume_rel_drift": (M1 - M0) / M0,
+        },
+        "ceilings": {
+            "pull_copy_GBs": round(pull_gbs, 1),
+            "pull_copy_ms": round(pull_ms, 5),
+            "plain_copy_GBs": round(copy_gbs, 1),
+            "hydro_algorithmic_over_pull_copy": round(achieved / pull_gbs, 4),
+            "hydro_measured_over_pull_copy": (round(traffic / (hydro_ms * 1e-3) / 1e9 / pull_gbs, 4)
+                                              if traffic else None),
         },
     }
     sim.close()

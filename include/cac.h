@@ -164,6 +164,16 @@ cac_status cac_set_launch(cac_handle *h, int bx, int by, int bz, int phase_tile,
  * V volume correction).  Synchronises.  For measurement only. */
 cac_status cac_profile_step(cac_handle *h, int nsteps, double *ms);
 
+/* Bandwidth ceiling of the hydrodynamic kernel's access pattern: reps
+ * launches of a kernel that pulls the 27 population planes from the upstream
+ * neighbours (periodic wrap) and stores them, with the tiling and load hints
+ * of the collide-stream kernel and none of its arithmetic (216 bytes moved per
+ * node).  *ms = average milliseconds per launch (HIP events on the handle's
+ * stream).  Overwrites both population buffers: the handle has no state
+ * afterwards (cac_step returns CAC_ERR_STATE until cac_set_state or
+ * cac_load_state).  Synchronises.  For measurement only. */
+cac_status cac_pull_copy_probe(cac_handle *h, int reps, double *ms);
+
 /* Size in bytes of a saved state (cac_save_state): a 64-byte header plus
  * 33 N floats (populations, phi with the current and the previous ghosts,
  * velocity, initial p*). */

@@ -59,6 +59,7 @@ SIGNATURES = {
     "cac_sync": (C.c_int, [_hp]),
     "cac_set_launch": (C.c_int, [_hp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
     "cac_profile_step": (C.c_int, [_hp, C.c_int, C.POINTER(C.c_double)]),
+    "cac_pull_copy_probe": (C.c_int, [_hp, C.c_int, C.POINTER(C.c_double)]),
     "cac_destroy": (C.c_int, [_hp]),
     "cac_state_bytes": (C.c_int, [_hp, C.POINTER(C.c_size_t)]),
     "cac_save_state": (C.c_int, [_hp, _vp, C.c_size_t]),
@@ -270,6 +271,13 @@ class Sim:
         ms = (C.c_double * 4)()
         self._check(self.lib.cac_profile_step(self.h, int(n), ms))
         return list(ms)
+
+    def pull_copy_probe(self, reps=20):
+        """Milliseconds per launch of the 27-plane pull copy (the collide-stream's
+        access pattern without its arithmetic).  Leaves the handle without a state."""
+        ms = C.c_double()
+        self._check(self.lib.cac_pull_copy_probe(self.h, int(reps), C.byref(ms)))
+        return ms.value
 
     def set_launch(self, bx, by, bz, use_graph=False, phase_tile=0):
         self._check(self.lib.cac_set_launch(self.h, int(bx), int(by), int(bz), int(phase_tile),

@@ -38,7 +38,12 @@ __global__ __launch_bounds__(NT) void k_hydro(Grid g, Tiling t, DevParams p, con
                                               const uint32_t *__restrict__ nbr, float *__restrict__ u,
                                               uint32_t *__restrict__ flag)
 {
-    hydro_node<NTL>(g, p, tile_node(g, t, xcd_tile(blockIdx.x, t.ntiles)), fin, fout, phi, nbr, u, flag);
+    // Workgroup order: with non-temporal loads nothing is re-read from L2, and
+    // the hardware's round-robin over the XCDs streams HBM best (3% faster on
+    // 256x256x128); with ordinary loads each XCD takes a contiguous range of
+    // tiles so that halo rows stay in its L2.
+    const uint32_t tile = NTL ? blockIdx.x : xcd_tile(blockIdx.x, t.ntiles);
+    hydro_node<NTL>(g, p, tile_node(g, t, tile), fin, fout, phi, nbr, u, flag);
 }
 
 template <int BX, int BY>

@@ -12,6 +12,7 @@
 
 #include "../../include/cac.h"
 #include "handle.hpp"
+#include "probe.hpp"
 
 using namespace cac;
 
@@ -549,6 +550,33 @@ cac_status cac_set_launch(cac_handle *h, int bx, int by, int bz, int phase_tile,
     h->use_graph = use_graph != 0;
     drop_graphs(h);
     return CAC_OK;
+}
+
+cac_status cac_pull_copy_probe(cac_handle *h, int reps, double *ms)
+{
+    if (!h || !ms || reps < 1) return CAC_ERR_ARG;
+    if (h->sub != 0) return fail(h, CAC_ERR_STATE, "a step was started with cac_debug_substep");
+    hipEvent_t e0, e1;
+    HIPCHK(h, hipEventCreate(&e0));
+    HIPCHK(h, hipEventCreate(&e1));
+    cac_status st = CAC_OK;
+    if (launch_pull_copy(h->g, h->t, h->F.f[0], h->F.f[1], h->stream) != hipSuccess ||
+        hipEventRecord(e0, h->stream) != hipSuccess)
+        st = fail(h, CAC_ERR_HIP, "pull-copy launch");
+    for (int k = 0; k < reps && st == CAC_OK; ++k)
+        if (launch_pull_copy(h->g, h->t, h->F.f[(k + 1) & 1], h->F.f[k & 1], h->stream) != hipSuccess)
+            st = fail(h, CAC_ERR_HIP, "pull-copy launch");
+    float t = 0.f;
+    if (st == CAC_OK && (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+        st = fail(h, CAC_ERR_HIP, "pull-copy timing");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // the populations are overwritten: a state must be set again before stepping
+    h->state = false;
+    tape_invalidate(h);
+    if (st == CAC_OK) *ms = (double)t / reps;
+    return st;
 }
 
 cac_status cac_profile_step(cac_handle *h, int nsteps, double *ms)
