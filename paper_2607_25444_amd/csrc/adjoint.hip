@@ -59,17 +59,27 @@ __global__ __launch_bounds__(256) void k_adj_vsum(uint32_t N, const uint8_t *__r
                                                   const float *__restrict__ pb, const float *__restrict__ phistar,
                                                   float eps, double *__restrict__ red)
 {
-    double a = 0.0, b = 0.0, c = 0.0;
+    // all loads first, at in-range indices (a node past N reads node 0 and is
+    // then skipped), so that they are in flight together
+    uint8_t so[ADJ_VSUM_PER_THREAD];
+    float v[ADJ_VSUM_PER_THREAD], q[ADJ_VSUM_PER_THREAD];
 #pragma unroll
     for (uint32_t r = 0; r < ADJ_VSUM_PER_THREAD; ++r) {
         const uint32_t n = (blockIdx.x * ADJ_VSUM_PER_THREAD + r) * 256u + threadIdx.x;
-        if (n < N && !solid[n]) {
-            const float v = phistar[n];
-            b += (double)v;
-            if (v > eps && v < 1.0f - eps) {
-                const double ch = (double)v * (1.0 - (double)v);
+        const uint32_t m = n < N ? n : 0u;
+        so[r] = n < N ? solid[m] : (uint8_t)1;
+        v[r] = phistar[m];
+        q[r] = pb[m];
+    }
+    double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+    for (uint32_t r = 0; r < ADJ_VSUM_PER_THREAD; ++r) {
+        if (!so[r]) {
+            b += (double)v[r];
+            if (v[r] > eps && v[r] < 1.0f - eps) {
+                const double ch = (double)v[r] * (1.0 - (double)v[r]);
                 c += ch;
-                a += (double)pb[n] * ch;
+                a += (double)q[r] * ch;
             }
         }
     }
@@ -125,7 +135,14 @@ __global__ __launch_bounds__(NT) void k_adj_main(Grid g, Tiling t, DevParams p, 
 // Transpose of the gradient / Laplacian stencils as a 2.5-D LDS stencil: a
 // workgroup owns a BX x BY column tile and marches up a z-chunk; LDS holds a
 // ring of three planes of the (grad x, y, z; Laplacian) cotangent records with
-// a halo of one.  Same sums as adj_assemble_node.
+// a halo of one.  The sums of adj_assemble_node, regrouped plane by plane with
+// the tensor-product weights t(0) = 4, t(+-1) = 1: per plane, from the 3 x 3
+// patch q around the column,
+//   X = sum_dy t(dy) [q.x(+1, dy) - q.x(-1, dy)],  Y likewise with q.y,
+//   Z = sum t(dx) t(dy) q.z,  tq = sum t(dx) t(dy) [q.w - q.w(0, 0)],  c = q.w(0, 0),
+// then over planes -1, 0, +1 (rolled up the column):
+//   -div = -(X_- + 4 X_0 + X_+ + Y_- + 4 Y_0 + Y_+ + Z_+ - Z_-) / 72,
+//   lap  = (tq_- + 4 tq_0 + tq_+ + 36 ((c_- - c_0) + (c_+ - c_0))) / 36.
 template <int BX, int BY>
 __global__ __launch_bounds__(BX *BY) void k_adj_assemble_lds(Grid g, PhaseTiling pt, AdjStep S)
 {
@@ -163,35 +180,47 @@ __global__ __launch_bounds__(BX *BY) void k_adj_assemble_lds(Grid g, PhaseTiling
         if (h0) dst[k0] = v0;
         if (h1) dst[k1] = v1;
     };
+    struct PS {
+        float X, Y, Z, tq, c;
+    };
+    const int c0 = (ly + 1) * AX + lx + 1;
+    auto psums = [&](int zz) {
+        const float4 *pl = sr[slot(zz)];
+        float4 q[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) q[j] = pl[c0 + (j / 3 - 1) * AX + (j % 3 - 1)];
+        PS r;
+        r.c = q[4].w;
+        r.X = (q[2].x - q[0].x) + 4.0f * (q[5].x - q[3].x) + (q[8].x - q[6].x);
+        r.Y = (q[6].y - q[0].y) + 4.0f * (q[7].y - q[1].y) + (q[8].y - q[2].y);
+        r.Z = (q[0].z + q[2].z + q[6].z + q[8].z) + 4.0f * (q[1].z + q[3].z + q[5].z + q[7].z) + 16.0f * q[4].z;
+        r.tq = (q[0].w - r.c) + (q[2].w - r.c) + (q[6].w - r.c) + (q[8].w - r.c) +
+               4.0f * ((q[1].w - r.c) + (q[3].w - r.c) + (q[5].w - r.c) + (q[7].w - r.c));
+        return r;
+    };
     fetch(z0 - 1);
     store(z0 - 1);
     fetch(z0);
     store(z0);
     fetch(z0 + 1);
-    const int c0 = (ly + 1) * AX + lx + 1;
+    __syncthreads();
+    PS sm = psums(z0 - 1), sc = psums(z0);
     for (int z = z0; z < z1; ++z) {
+        // One barrier per plane: this plane reads only the slot of z + 1; the
+        // store below (slot of z + 1) overwrites plane z - 2, which no wave
+        // still reads (waves are at most one plane apart).
         store(z + 1);
         __syncthreads();
         if (z + 1 < z1) fetch(z + 2);  // lands while this plane computes
+        const PS sp = psums(z + 1);
         if (col_in) {
-            const float L0 = sr[slot(z)][c0].w;
-            float dv = 0.f, lp = 0.f;
-            static_for<27>([&](auto K) {
-                constexpr int kk = K;
-                constexpr int dx = kk % 3 - 1, dy = (kk / 3) % 3 - 1, dz = kk / 9 - 1;
-                if constexpr (kk != 13) {
-                    constexpr float w = tw(dx) * tw(dy) * tw(dz);
-                    const float4 q = sr[slot(z + dz)][c0 + dy * AX + dx];
-                    if constexpr (dx != 0) dv += ((float)dx * w * (1.0f / 72.0f)) * q.x;
-                    if constexpr (dy != 0) dv += ((float)dy * w * (1.0f / 72.0f)) * q.y;
-                    if constexpr (dz != 0) dv += ((float)dz * w * (1.0f / 72.0f)) * q.z;
-                    lp += (w * (1.0f / 36.0f)) * (q.w - L0);
-                }
-            });
+            const float dv = (sm.X + 4.0f * sc.X + sp.X + sm.Y + 4.0f * sc.Y + sp.Y + sp.Z - sm.Z) * (1.0f / 72.0f);
+            const float lp = (sm.tq + 4.0f * sc.tq + sp.tq + 36.0f * ((sm.c - sc.c) + (sp.c - sc.c))) * (1.0f / 36.0f);
             const uint32_t n = (uint32_t)x + (uint32_t)y * (uint32_t)g.nx + (uint32_t)z * g.nxny;
             S.pb_out[n] = recl[n] + lp - dv;
         }
-        __syncthreads();  // the slot of plane z - 1 is overwritten next
+        sm = sc;
+        sc = sp;
     }
 }
 
