@@ -229,6 +229,99 @@ def random_geometry(shape, seed, n_blocks=3) -> np.ndarray:
     return s.reshape(-1)
 
 
+# ---------------------------------------------------------------- curved and porous solids
+# Voxel geometries beyond planar walls (the paper's outlook, Sec. IV): the wall
+# normal and the donor are reconstructed from the mask alone, so these masks
+# exercise staircase corners, convex and concave edges and the tie-breaks.
+
+def ball_mask(shape, centre, R, periodic_xy=True) -> np.ndarray:
+    """1 on nodes within distance R of centre (x and y distances periodic)."""
+    nx, ny, nz = shape
+    m = np.zeros((nz, ny, nx), np.uint8)
+    r = int(np.ceil(R)) + 1
+    zs = np.arange(max(0, int(np.floor(centre[2])) - r), min(nz, int(np.ceil(centre[2])) + r + 1))
+    ys = np.arange(int(np.floor(centre[1])) - r, int(np.ceil(centre[1])) + r + 1)
+    xs = np.arange(int(np.floor(centre[0])) - r, int(np.ceil(centre[0])) + r + 1)
+    if not periodic_xy:
+        ys, xs = ys[(ys >= 0) & (ys < ny)], xs[(xs >= 0) & (xs < nx)]
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    inside = (X - centre[0]) ** 2 + (Y - centre[1]) ** 2 + (Z - centre[2]) ** 2 <= R * R
+    m[Z[inside], Y[inside] % ny, X[inside] % nx] = 1
+    return m.reshape(-1)
+
+
+def sphere_substrate(shape=(64, 64, 48), Rs=14.0, R=10.0, theta_deg=60.0, delta=4.0, **pkw) -> Workload:
+    """Sessile droplet on a voxelised solid sphere that rests sunk into the bottom
+    wall; the droplet overlaps the sphere's top."""
+    nx, ny, nz = shape
+    c = ((nx - 1) / 2, (ny - 1) / 2, 0.5 + 0.6 * Rs)
+    solid = np.maximum(flat_walls(shape), ball_mask(shape, c, Rs))
+    phi0 = tanh_droplet(shape, (c[0], c[1], c[2] + Rs + 0.3 * R), R, delta)
+    return Workload(f"sphere_substrate_{nx}x{ny}x{nz}", shape, solid, uniform_theta(shape, theta_deg),
+                    phi0.astype(np.float32), default_params(delta=delta, **pkw), 0,
+                    dict(Rs=Rs, R=R, theta_deg=theta_deg, centre=c))
+
+
+def cylinder_substrate(shape=(64, 40, 48), Rc=10.0, R=9.0, theta_deg=90.0, delta=4.0, **pkw) -> Workload:
+    """Droplet on a voxelised solid cylinder (axis along y) lying on the bottom wall."""
+    nx, ny, nz = shape
+    x, y, z = grid(shape)
+    cx, cz = (nx - 1) / 2, 0.5 + 0.8 * Rc
+    cyl = (((x - cx) ** 2 + (z - cz) ** 2) <= Rc * Rc).astype(np.uint8).reshape(-1)
+    solid = np.maximum(flat_walls(shape), cyl)
+    phi0 = tanh_droplet(shape, (cx, (ny - 1) / 2, cz + Rc + 0.3 * R), R, delta)
+    return Workload(f"cylinder_substrate_{nx}x{ny}x{nz}", shape, solid, uniform_theta(shape, theta_deg),
+                    phi0.astype(np.float32), default_params(delta=delta, **pkw), 0,
+                    dict(Rc=Rc, R=R, theta_deg=theta_deg))
+
+
+def rough_wall(shape=(64, 64, 40), seed=0, n_pillars=24, R=12.0, delta=4.0, **pkw) -> Workload:
+    """Droplet on a rough bottom wall: random square pillars 2-4 voxels wide and
+    1-4 high; contact angle per wall node uniform in [40, 140] degrees."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = shape
+    s = flat_walls(shape).reshape(nz, ny, nx).copy()
+    for _ in range(n_pillars):
+        w, h = rng.integers(2, 5), rng.integers(1, 5)
+        x0, y0 = rng.integers(0, nx), rng.integers(0, ny)
+        for dz in range(1, 1 + h):
+            for dy in range(w):
+                for dx in range(w):
+                    s[dz, (y0 + dy) % ny, (x0 + dx) % nx] = 1
+    theta = np.deg2rad(rng.uniform(40.0, 140.0, nx * ny * nz)).astype(np.float32)
+    phi0 = tanh_droplet(shape, ((nx - 1) / 2, (ny - 1) / 2, 3.5 + 0.6 * R), R, delta)
+    return Workload(f"rough_wall_{nx}x{ny}x{nz}", shape, s.reshape(-1), theta, phi0.astype(np.float32),
+                    default_params(delta=delta, **pkw), 0, dict(R=R, seed=seed))
+
+
+def porous_packing(shape=(64, 64, 64), seed=0, n_spheres=14, r_lo=4.0, r_hi=8.0, R=None, delta=4.0,
+                   **pkw) -> Workload:
+    """Droplet above a random packing of (overlapping) solid spheres filling the
+    lower half of the box (periodic in x and y); contact angle per wall node
+    uniform in [40, 140] degrees."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = shape
+    solid = flat_walls(shape)
+    top = 0.0
+    for _ in range(n_spheres):
+        r = rng.uniform(r_lo, r_hi)
+        c = (rng.uniform(0, nx), rng.uniform(0, ny), rng.uniform(1.0 + r * 0.5, nz / 2 - r * 0.5))
+        top = max(top, c[2] + r)
+        solid = np.maximum(solid, ball_mask(shape, c, r))
+    R = R if R is not None else min(nx, ny) / 5.0
+    theta = np.deg2rad(rng.uniform(40.0, 140.0, nx * ny * nz)).astype(np.float32)
+    zc = min(top + 0.6 * R, nz - 2.0 - R)
+    phi0 = tanh_droplet(shape, ((nx - 1) / 2, (ny - 1) / 2, zc), R, delta)
+    return Workload(f"porous_{nx}x{ny}x{nz}", shape, solid, theta, phi0.astype(np.float32),
+                    default_params(delta=delta, **pkw), 0, dict(R=R, seed=seed, n_spheres=n_spheres))
+
+
+def porous_256(seed=0) -> Workload:
+    """Throughput case of the porous family: 256x256x128, 60 spheres of radius
+    8-16 in the lower half, droplet R = 32 above."""
+    return porous_packing((256, 256, 128), seed=seed, n_spheres=60, r_lo=8.0, r_hi=16.0, R=32.0)
+
+
 def params_dict(w: Workload) -> dict:
     return dict(w.params)
 
