@@ -228,7 +228,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="spreading", choices=["spreading", "orifice", "porous", "sessile"])
+    ap.add_argument("--workload", default="spreading", choices=["spreading", "orifice", "porous", "impact", "sessile"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -262,6 +262,8 @@ def main():
         w = W.orifice_192(args.seed)
     elif args.workload == "porous":
         w = W.porous_256(args.seed)
+    elif args.workload == "impact":
+        w = W.impact_256()
     else:
         w = W.sessile_32(60.0)
     launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else tuning.launch_for(w.shape)
@@ -272,7 +274,7 @@ def main():
     sim = capi.Sim(w.shape, w.params, device=dev)
     sim.set_launch(*launch)
     sim.set_geometry(w.solid, w.theta)
-    sim.set_state(w.phi0)
+    sim.set_state(w.phi0, w.meta.get("u0"))
     M0 = sim.volume()
 
     sim.step(args.warmup)

@@ -229,6 +229,33 @@ def random_geometry(shape, seed, n_blocks=3) -> np.ndarray:
     return s.reshape(-1)
 
 
+# ---------------------------------------------------------------- droplet impact (Sec. III C)
+
+def impact(shape=(64, 64, 48), R=12.0, We=10.0, theta_deg=130.0, delta=4.0, **pkw) -> Workload:
+    """Droplet impact on a hydrophobic wall at liquid-to-gas density ratio 1000:
+    rho_l = 10, rho_g = 0.01, nu_l = nu_g = 0.05, sigma = 0.02, theta = 130 deg,
+    no gravity.  The droplet's lower interface touches the wall (centre at z =
+    1/2 + R) and it moves towards the wall with U0 = sqrt(We sigma / (rho_l D0)),
+    D0 = 2R; the initial velocity is -U0 phi0 along z (the gas at rest)."""
+    nx, ny, nz = shape
+    prm = dict(rho_l=10.0, rho_g=0.01, nu_l=0.05, nu_g=0.05, sigma=0.02, delta=delta)
+    prm.update(pkw)
+    U0 = float(np.sqrt(We * prm["sigma"] / (prm["rho_l"] * 2.0 * R)))
+    phi0 = tanh_droplet(shape, ((nx - 1) / 2, (ny - 1) / 2, 0.5 + R), R, delta).astype(np.float32)
+    N = nx * ny * nz
+    u0 = np.zeros(3 * N, np.float32)
+    u0[2 * N:] = -U0 * phi0
+    w = Workload(f"impact_{nx}x{ny}x{nz}", shape, flat_walls(shape), uniform_theta(shape, theta_deg), phi0,
+                 default_params(**prm), 0, dict(R=R, We=We, U0=U0, theta_deg=theta_deg))
+    w.meta["u0"] = u0
+    return w
+
+
+def impact_256(We=10.0) -> Workload:
+    """Throughput case of the impact family: 256^3, R0 = 40."""
+    return impact((256, 256, 256), R=40.0, We=We)
+
+
 # ---------------------------------------------------------------- curved and porous solids
 # Voxel geometries beyond planar walls (the paper's outlook, Sec. IV): the wall
 # normal and the donor are reconstructed from the mask alone, so these masks
