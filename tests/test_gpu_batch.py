@@ -135,6 +135,27 @@ def test_autotune_keeps_state_and_caches(tmp_path):
     b2.close()
 
 
+def test_full_batch_sampled_domains():
+    """The benchmark's batch at full size (64 domains, edges 32-128, autotuned
+    schedule), 5 steps: the smallest, the median and the largest domain equal
+    the same domain advanced alone (which is oracle-checked)."""
+    from paper_2607_25444_amd import capi
+    ws = W.batch_domains(0)
+    b = capi.Batch(ws)
+    b.autotune(None, trial_steps=2)
+    b.step(5)
+    order = np.argsort([w.N for w in ws], kind="stable")
+    for k in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        w = ws[k]
+        phi_b, u_b = _batch_fields(b, k)
+        phi_s, u_s = _single(w, 5)
+        fl = w.solid == 0
+        print(f"[batch] domain {k} {w.shape}: dphi {np.abs(phi_b - phi_s)[fl].max():.2e}", flush=True)
+        assert np.abs(phi_b - phi_s)[fl].max() <= 2e-6
+        assert np.abs(u_b - u_s).max() <= 2e-5 * max(np.abs(u_s).max(), 1e-9) + 1e-12
+    b.close()
+
+
 def test_batch_watchdog():
     """A NaN in one domain's initial phase field is reported for the batch."""
     from paper_2607_25444_amd import capi
