@@ -268,7 +268,17 @@ static void phase_shape(const Grid &g, int code, int &bx, int &by)
     case 6: bx = 128; by = 4; return;
     default: break;
     }
-    bx = g.nx >= 64 ? 64 : (g.nx >= 32 ? 32 : 16);
+    // the widest of 64, 32, 16 that divides nx (no half-empty tile at the
+    // row end: 96 -> 32 x 16 runs 0.021 instead of 0.031 ms on 96^3), else
+    // the widest that fits
+    if (g.nx % 64 == 0)
+        bx = 64;
+    else if (g.nx % 32 == 0)
+        bx = 32;
+    else if (g.nx % 16 == 0)
+        bx = 16;
+    else
+        bx = g.nx >= 64 ? 64 : (g.nx >= 32 ? 32 : 16);
     by = bx == 64 ? 8 : 16;
 }
 

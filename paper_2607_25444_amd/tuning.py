@@ -27,7 +27,9 @@ def launch_for(shape):
     if nx in (128, 256, 512):
         bx, by, bz = nx, max(1, 512 // nx) if nx > 128 else 2, 1
     else:
-        bx = 64 if nx >= 64 else (32 if nx >= 32 else 16)
+        # the widest of 64, 32, 16 that divides nx (no half-empty tile at the row end), else the widest that fits
+        div = [b for b in (64, 32, 16) if nx % b == 0]
+        bx = div[0] if div else (64 if nx >= 64 else (32 if nx >= 32 else 16))
         by = max(1, min(4, 256 // bx))
         bz = 256 // (bx * by)
     return (bx, by, bz, 1 if n <= (1 << 22) else 0, 0)
