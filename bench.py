@@ -110,7 +110,7 @@ def bench_batch(torch, capi, W, steps, warmup, seed, singles=True, tune_cache=No
     b = capi.Batch(ws)
     t_init = time.perf_counter() - t0
     ndom, ntot, nfl = b.info()
-    tune_ms = b.autotune(tune_cache, trial_steps=3)
+    tune_ms = b.autotune(tune_cache, trial_steps=6)
     sched = b.schedule()
     b.step(warmup)
     b.sync()

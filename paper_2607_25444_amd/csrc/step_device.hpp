@@ -298,11 +298,10 @@ __host__ __device__ __forceinline__ void pair_moments(const float (&f)[27], floa
 //   step and the 27-plane sets are far larger than the caches, so they should
 //   not evict phi, u and the masks, which the stencils re-read.  NTL = true
 //   reads them with the same hint; that pays when a workgroup covers whole
-//   rows of a large lattice (the single-lattice kernel), whose y and z
-//   neighbour rows are pulled by workgroups running at the same time.  The
-//   batched kernel's smaller tiles re-read neighbour rows later, from L2, and
-//   run faster with ordinary loads (NTL = false; about 10% on the 64-domain
-//   batch).
+//   rows (bx = nx), whose y and z neighbour rows are pulled by workgroups
+//   running at the same time.  Narrower tiles re-read neighbour rows later,
+//   from L2, and run faster with ordinary loads (NTL = false; about 10% on
+//   the 64-domain batch, 12% on 256 x 256 x 128).
 template <bool NTL>
 __device__ __forceinline__ void hydro_node(const Grid &g, const DevParams &p, const Node &nd,
                                            const float *__restrict__ fin, float *__restrict__ fout,
