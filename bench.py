@@ -50,11 +50,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(n_fluid_per_launch):
+def measured_traffic(workload_name):
     """HBM bytes per hydro launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source; else None."""
+    if it was taken on this workload and on the current kernel source; else None."""
     p = os.path.join(ROOT, "profiles", "hydro_traffic_spreading_256x256x128.json")
-    if not os.path.exists(p):
+    if workload_name != "spreading_256x256x128" or not os.path.exists(p):
         return None
     d = json.load(open(p))
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
@@ -228,7 +228,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="spreading", choices=["spreading", "orifice", "porous", "impact", "sessile"])
+    ap.add_argument("--workload", default="spreading", choices=["spreading", "orifice", "porous", "impact", "spreading512", "sessile"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -264,6 +264,8 @@ def main():
         w = W.porous_256(args.seed)
     elif args.workload == "impact":
         w = W.impact_256()
+    elif args.workload == "spreading512":
+        w = W.spreading_512()
     else:
         w = W.sessile_32(60.0)
     launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else tuning.launch_for(w.shape)
@@ -299,7 +301,7 @@ def main():
     kavg = [v / kp for v in kms]
     hydro_ms = kavg[1]
     achieved = w.n_fluid * HYDRO_BYTES_PER_LU / (hydro_ms * 1e-3) / 1e9
-    traffic = measured_traffic(w.n_fluid)
+    traffic = measured_traffic(w.name)
     M1 = sim.volume()
     log(f"[bench] kernel ms/step W={kavg[0]:.4f} H={kavg[1]:.4f} P={kavg[2]:.4f} V={kavg[3]:.4f}; "
         f"hydro {achieved:.0f} GB/s; volume drift {(M1 - M0) / M0:.2e}")

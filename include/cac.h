@@ -82,7 +82,7 @@ cac_status cac_default_params(cac_params *p);
 /* Create a handle for an nx * ny * nz lattice on the current HIP device.
  * hip_stream: hipStream_t to order all work on (NULL: the null stream).
  * alloc/alloc_user: allocation callback (NULL: hipMalloc, freed by cac_destroy).
- * Errors: CAC_ERR_ARG if a size is < 2 or 27 * N does not fit in 31 bits, or
+ * Errors: CAC_ERR_ARG if a size is < 2 or 27 * N does not fit in 32 bits, or
  * a parameter is out of range (densities or viscosities <= 0, delta <= 0, D < 0). */
 cac_status cac_init(cac_handle **h, int nx, int ny, int nz, const cac_params *p, cac_alloc_fn alloc,
                     void *alloc_user, void *hip_stream);

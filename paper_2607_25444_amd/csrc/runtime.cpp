@@ -286,7 +286,8 @@ cac_status cac_init(cac_handle **hp, int nx, int ny, int nz, const cac_params *p
     // every axis needs two nodes: the MUSCL stencil reaches two nodes along each axis
     if (nx < 2 || ny < 2 || nz < 2) return CAC_ERR_ARG;
     const unsigned long long N = (unsigned long long)nx * ny * nz;
-    if (27ull * N >= (1ull << 31)) return CAC_ERR_ARG;
+    // population index i * N + n is an unsigned 32-bit integer in the kernels
+    if (27ull * N > 0xFFFFFFFFull) return CAC_ERR_ARG;
     if (!valid_params(*p)) return CAC_ERR_ARG;
     cac_handle *h = new cac_handle();
     h->prm = *p;
@@ -414,7 +415,8 @@ cac_status cac_wall_tables(int nx, int ny, int nz, const uint8_t *solid, int *n_
 {
     if (nx < 1 || ny < 1 || nz < 1 || !solid || !n_b) return CAC_ERR_ARG;
     const unsigned long long N = (unsigned long long)nx * ny * nz;
-    if (27ull * N >= (1ull << 31)) return CAC_ERR_ARG;
+    // population index i * N + n is an unsigned 32-bit integer in the kernels
+    if (27ull * N > 0xFFFFFFFFull) return CAC_ERR_ARG;
     Grid g{};
     g.nx = nx;
     g.ny = ny;

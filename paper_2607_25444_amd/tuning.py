@@ -17,19 +17,23 @@ PHASE_TILES = {1: (64, 8), 2: (64, 4), 3: (32, 8), 4: (32, 16), 5: (16, 16), 6: 
 def launch_for(shape):
     """(bx, by, bz, use_graph, phase_tile) for a lattice of this shape.
 
-    A row-wide tile (bx = nx, a power of two from 128 to 512) lets the
-    collide-stream read populations with non-temporal loads in the hardware
-    workgroup order; other widths take 64-wide tiles with ordinary loads
-    (measured: 0.354 vs 0.397 ms on 256 x 256 x 128, 12.3 vs 11.8 GLUPS for the
-    plain step on 128 x 128 x 64)."""
+    128- and 256-wide lattices take a row-wide tile (bx = nx), with which the
+    collide-stream reads populations with non-temporal loads in the hardware
+    workgroup order (0.354 vs 0.397 ms on 256 x 256 x 128; 12.3 vs 11.8 GLUPS
+    for the plain step on 128 x 128 x 64).  Other widths take the widest of
+    256, 128, 64, 32, 16 that divides nx (no half-empty tile at the row end)
+    with ordinary loads; a 512-wide row-wide tile was measured slower than
+    256 x 2 (16.6 vs 17.7 GLUPS on 512^3)."""
     nx, ny, nz = shape
     n = nx * ny * nz
-    if nx in (128, 256, 512):
-        bx, by, bz = nx, max(1, 512 // nx) if nx > 128 else 2, 1
+    if nx in (128, 256):
+        bx, by, bz = nx, 2, 1
     else:
-        # the widest of 64, 32, 16 that divides nx (no half-empty tile at the row end), else the widest that fits
-        div = [b for b in (64, 32, 16) if nx % b == 0]
+        div = [b for b in (256, 128, 64, 32, 16) if nx % b == 0]
         bx = div[0] if div else (64 if nx >= 64 else (32 if nx >= 32 else 16))
-        by = max(1, min(4, 256 // bx))
-        bz = 256 // (bx * by)
+        if bx >= 128:
+            by, bz = 512 // bx, 1
+        else:
+            by = max(1, min(4, 256 // bx))
+            bz = 256 // (bx * by)
     return (bx, by, bz, 1 if n <= (1 << 22) else 0, 0)

@@ -121,6 +121,19 @@ def spreading_256(seed=0) -> Workload:
                     dict(R=R, theta_deg=theta, Oh=oh, tau_i=float(np.sqrt(rho * R ** 3 / sigma))))
 
 
+def spreading_512(theta_deg=90.0) -> Workload:
+    """The paper's spreading lattice (Sec. III B): 512^3, R0 = 80 touching the
+    wall, rho = 1, nu = 0.05, sigma = 0.02 (Oh_R0 = 3.95e-2), interface width 4."""
+    shape = (512, 512, 512)
+    nx, ny, nz = shape
+    R = 80.0
+    solid = flat_walls(shape)
+    phi0 = tanh_droplet(shape, ((nx - 1) / 2, (ny - 1) / 2, 0.5 + R), R, 4.0)
+    return Workload("spreading_512x512x512", shape, solid, uniform_theta(shape, theta_deg),
+                    phi0.astype(np.float32), default_params(nu_l=0.05, nu_g=0.05, sigma=0.02), 0,
+                    dict(R=R, theta_deg=theta_deg))
+
+
 def orifice_plate_mask(shape, z_lo, thickness, hole_d) -> np.ndarray:
     nx, ny, nz = shape
     x, y, z = grid(shape)

@@ -57,6 +57,8 @@ def test_init_rejects_bad_arguments(lib):
     cb = capi.ALLOC_FN(lambda n, u: 0)
     assert lib.cac_init(C.byref(h), 0, 4, 4, C.byref(p), cb, None, None) == capi.CAC_ERR_ARG
     assert lib.cac_init(C.byref(h), 1024, 1024, 1024, C.byref(p), cb, None, None) == capi.CAC_ERR_ARG
+    # 27 N must fit in 32 bits (543^3 does not; 512^3 does)
+    assert lib.cac_init(C.byref(h), 543, 543, 543, C.byref(p), cb, None, None) == capi.CAC_ERR_ARG
     p.delta = 0.0
     assert lib.cac_init(C.byref(h), 8, 8, 8, C.byref(p), cb, None, None) == capi.CAC_ERR_ARG
     assert lib.cac_init(None, 8, 8, 8, C.byref(p), cb, None, None) == capi.CAC_ERR_ARG

@@ -126,7 +126,7 @@ def test_sessile_200_steps(orc, wc):
 
 
 @pytest.mark.parametrize("launch", [None, (16, 4, 4, 0, 5), (32, 2, 4, 1, 3), (16, 8, 4, 0, 2), (64, 2, 2, 0, 1),
-                                    (128, 2, 1, 0, 6), (32, 4, 4, 0, 4)])
+                                    (128, 2, 1, 0, 6), (32, 4, 4, 0, 4), (256, 2, 1, 0, 1), (512, 1, 1, 1, 3)])
 def test_ragged_tiles(orc, launch):
     """A grid that fills no tile exactly (70 x 37 x 19), random solids, 20 steps."""
     shape = (70, 37, 19)
@@ -134,6 +134,19 @@ def test_ragged_tiles(orc, launch):
     solid = W.random_geometry(shape, 11, n_blocks=6)
     phi0 = W.tanh_droplet(shape, (30.2, 17.7, 7.1), 6.0, 4.0).astype(np.float32)
     w = W.Workload("ragged", shape, solid, W.uniform_theta(shape, 75.0), phi0, W.default_params(), 0)
+    o = oracle_run(orc, w, 20)
+    g = gpu_run(w, 20, launch=launch)
+    _cmp(g, o, w, orc, 5e-6, 5e-5)
+
+
+@pytest.mark.parametrize("launch", [(128, 2, 1, 0, 1), (128, 1, 2, 1, 3)])
+def test_row_wide_tiles(orc, launch):
+    """A lattice exactly one 128-wide tile across (non-temporal population loads
+    in the hardware workgroup order), random solids, 20 steps."""
+    shape = (128, 10, 12)
+    solid = W.random_geometry(shape, 13, n_blocks=5)
+    phi0 = W.tanh_droplet(shape, (60.3, 4.6, 5.2), 5.0, 4.0).astype(np.float32)
+    w = W.Workload("row_wide", shape, solid, W.uniform_theta(shape, 70.0), phi0, W.default_params(), 0)
     o = oracle_run(orc, w, 20)
     g = gpu_run(w, 20, launch=launch)
     _cmp(g, o, w, orc, 5e-6, 5e-5)
@@ -195,6 +208,39 @@ def test_full_size_one_step(orc, name):
     o = oracle_run(orc, w, 1)
     g = gpu_run(w, 1, launch=tuning.launch_for(w.shape))
     _cmp(g, o, w, orc, 2e-6, 1e-5, with_f=False)
+
+
+def test_512_cubed_lattice():
+    """The paper's 512^3 spreading lattice (27 N above 2^31: population indices
+    use the full unsigned 32-bit range): two steps in the launch the benchmark
+    uses (256 x 2 tiles, ordinary loads) and in row-wide 512 x 1 tiles
+    (non-temporal loads, hardware workgroup order) agree on every node
+    (the per-node arithmetic is the same; only the FP64 order of the volume
+    sums differs), stay finite and keep the phase-field volume."""
+    from paper_2607_25444_amd import capi, tuning
+    w = W.spreading_512()
+    assert 27 * w.N > 2 ** 31
+    fl = w.solid == 0
+    M0 = float(w.phi0.astype(np.float64)[fl].sum())
+    out = []
+    for launch in (tuning.launch_for(w.shape), (512, 1, 1, 0, 0)):
+        print(f"[512^3] launch {launch}", flush=True)
+        s = capi.Sim(w.shape, w.params)
+        s.set_launch(*launch)
+        s.set_geometry(w.solid, w.theta)
+        s.set_state(w.phi0)
+        s.step(2)
+        phi, u, _ = s.fields()
+        vol = s.volume()
+        s.sync()
+        out.append((phi.cpu().numpy(), u.cpu().numpy(), vol))
+        s.close()
+        del phi, u
+    (pa, ua, va), (pb, ub, vb) = out
+    assert np.isfinite(pa).all() and np.isfinite(ua).all()
+    assert np.abs(pa - pb)[fl].max() <= 2e-6
+    assert np.abs(ua - ub).max() <= 2e-5 * max(np.abs(ua).max(), 1e-9)
+    assert va == pytest.approx(M0, rel=2e-7) and vb == pytest.approx(M0, rel=2e-7)
 
 
 def test_watchdog_reports_non_finite_values():
