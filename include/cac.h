@@ -164,6 +164,18 @@ cac_status cac_set_launch(cac_handle *h, int bx, int by, int bz, int phase_tile,
  * V volume correction).  Synchronises.  For measurement only. */
 cac_status cac_profile_step(cac_handle *h, int nsteps, double *ms);
 
+/* Debug modes (flags, OR-ed; 0 = off), checks of the race-freedom and of the
+ * data the step never reads (results must stay bitwise the same):
+ *   CAC_DEBUG_POISON: every cac_set_state / cac_load_state afterwards fills
+ *     with quiet NaNs the populations and velocity on solid nodes and phi and
+ *     the compressive flux on solid nodes without a fluid neighbour (values the
+ *     step must never use);
+ *   CAC_DEBUG_REVERSE_ORDER: the ghost, hydrodynamic and phase kernels take
+ *     their workgroups in reverse order from the next step on.
+ * Errors: CAC_ERR_ARG for an unknown flag. */
+enum { CAC_DEBUG_POISON = 1, CAC_DEBUG_REVERSE_ORDER = 2 };
+cac_status cac_set_debug(cac_handle *h, int flags);
+
 /* Bandwidth ceiling of the hydrodynamic kernel's access pattern: reps
  * launches of a kernel that pulls the 27 population planes from the upstream
  * neighbours (periodic wrap) and stores them, with the tiling and load hints

@@ -18,6 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcac.so")
 
 CAC_OK, CAC_ERR_ARG, CAC_ERR_GEOMETRY, CAC_ERR_HIP, CAC_ERR_NONFINITE, CAC_ERR_STATE, CAC_ERR_ALLOC = range(7)
+CAC_DEBUG_POISON, CAC_DEBUG_REVERSE_ORDER = 1, 2
 
 
 class CacError(RuntimeError):
@@ -60,6 +61,7 @@ SIGNATURES = {
     "cac_set_launch": (C.c_int, [_hp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
     "cac_profile_step": (C.c_int, [_hp, C.c_int, C.POINTER(C.c_double)]),
     "cac_pull_copy_probe": (C.c_int, [_hp, C.c_int, C.POINTER(C.c_double)]),
+    "cac_set_debug": (C.c_int, [_hp, C.c_int]),
     "cac_destroy": (C.c_int, [_hp]),
     "cac_state_bytes": (C.c_int, [_hp, C.POINTER(C.c_size_t)]),
     "cac_save_state": (C.c_int, [_hp, _vp, C.c_size_t]),
@@ -271,6 +273,13 @@ class Sim:
         ms = (C.c_double * 4)()
         self._check(self.lib.cac_profile_step(self.h, int(n), ms))
         return list(ms)
+
+    def set_debug(self, poison=False, reverse_order=False):
+        """NaN poisoning of never-read data (at the next set_state/load_state) and
+        reverse workgroup order (from the next step); results must not change."""
+        self._check(self.lib.cac_set_debug(self.h, (CAC_DEBUG_POISON if poison else 0) |
+                                           (CAC_DEBUG_REVERSE_ORDER if reverse_order else 0)))
+        return self
 
     def pull_copy_probe(self, reps=20):
         """Milliseconds per launch of the 27-plane pull copy (the collide-stream's

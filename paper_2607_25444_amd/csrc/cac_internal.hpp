@@ -58,6 +58,7 @@ struct DevParams {
     int volume_correction;
     int wall_compression;
     int variable_density;    // drho != 0: pressure and viscous corrections are live
+    int rev_order;           // debug: W, H and P take their workgroups in reverse order
 };
 
 struct Grid {
@@ -154,6 +155,7 @@ uint32_t phase_tiles(const Grid &g, const Tiling &t);  // workgroups (and FP64 p
 uint32_t phase_tiles_max(const Grid &g);                // over every phase tile shape
 hipError_t launch_volume(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, int pnext,
                          hipStream_t s);
+hipError_t launch_poison(const Grid &g, const Fields &F, hipStream_t s);  // debug (k_poison)
 hipError_t launch_init(const Grid &g, const Fields &F, int fcur, const float *u0, const float *ps0,
                        hipStream_t s);
 hipError_t launch_mass(const Grid &g, const Tiling &t, const Fields &F, const float *phi, double *out,

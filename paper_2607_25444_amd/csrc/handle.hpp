@@ -37,6 +37,7 @@ struct cac_handle {
     int nskip = 0;
     // graph replay of two steps (even/odd buffer parity)
     bool use_graph = false;
+    int debug = 0;              // CAC_DEBUG_* flags (cac_set_debug)
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     hipStream_t cap_stream = nullptr;  // capture needs a stream other than the null stream
     long long geom_serial = 0;   // incremented by every cac_set_geometry

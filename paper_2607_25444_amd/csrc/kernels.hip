@@ -28,7 +28,8 @@ __global__ __launch_bounds__(256) void k_ghost(Grid g, DevParams p, const int32_
                                                const float *__restrict__ phi_old, const uint32_t *__restrict__ nbr,
                                                float *__restrict__ a)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t b = p.rev_order ? gridDim.x - 1u - blockIdx.x : blockIdx.x;
+    const int k = (int)(b * blockDim.x + threadIdx.x);
     if (k < nwall) ghost_node(g, p, k, widx, wq, wn, theta, phi_cur, phi_old, nbr, a);
 }
 
@@ -42,7 +43,8 @@ __global__ __launch_bounds__(NT) void k_hydro(Grid g, Tiling t, DevParams p, con
     // the hardware's round-robin over the XCDs streams HBM best (3% faster on
     // 256x256x128); with ordinary loads each XCD takes a contiguous range of
     // tiles so that halo rows stay in its L2.
-    const uint32_t tile = NTL ? blockIdx.x : xcd_tile(blockIdx.x, t.ntiles);
+    const uint32_t b = p.rev_order ? gridDim.x - 1u - blockIdx.x : blockIdx.x;
+    const uint32_t tile = NTL ? b : xcd_tile(b, t.ntiles);
     hydro_node<NTL>(g, p, tile_node(g, t, tile), fin, fout, phi, nbr, u, flag);
 }
 
@@ -52,8 +54,38 @@ __global__ __launch_bounds__(BX *BY) void k_phase(Grid g, PhaseTiling pt, DevPar
                                                   const float *__restrict__ aw, const uint8_t *__restrict__ solid,
                                                   double2 *__restrict__ partial, uint32_t *__restrict__ flag)
 {
-    const uint32_t tile = xcd_tile(blockIdx.x, pt.ntiles);
+    const uint32_t tile = xcd_tile(p.rev_order ? gridDim.x - 1u - blockIdx.x : blockIdx.x, pt.ntiles);
     phase_tile<BX, BY>(g, pt, p, tile, phi, phi_out, u, aw, solid, partial + tile, flag);
+}
+
+// Debug: quiet NaNs into every value the step must never read -- populations
+// and velocity on solid nodes, phi and the compressive flux on solid nodes
+// with no fluid neighbour -- so that a read the design excludes shows up in
+// the fluid results.
+__global__ __launch_bounds__(256) void k_poison(Grid g, const uint32_t *__restrict__ nbr, float *__restrict__ f0,
+                                                float *__restrict__ f1, float *__restrict__ phi0,
+                                                float *__restrict__ phi1, float *__restrict__ u, float *__restrict__ a)
+{
+    const uint32_t n = blockIdx.x * 256u + threadIdx.x;
+    if (n >= g.N) return;
+    const uint32_t m = nbr[n];
+    if (!(m & 1u)) return;
+    const uint32_t N = g.N;
+    const float q = __builtin_nanf("");
+    for (uint32_t i = 0; i < 27u; ++i) {
+        f0[i * N + n] = q;
+        f1[i * N + n] = q;
+    }
+    u[n] = q;
+    u[N + n] = q;
+    u[2u * N + n] = q;
+    if (((~m) & 0x07FFFFFEu) == 0u) {
+        phi0[n] = q;
+        phi1[n] = q;
+        a[n] = q;
+        a[N + n] = q;
+        a[2u * N + n] = q;
+    }
 }
 
 // ------------------------------------------------------------------ V: volume
@@ -348,6 +380,12 @@ hipError_t launch_volume_copy(const Grid &g, const Tiling &t, const DevParams &p
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_vol_copy<<<blocks_for(g.N, 256), 256, 0, s>>>(g.N, F.solid, phistar, phihat, out, F.scal, p.eps_phi);
+    return hipGetLastError();
+}
+
+hipError_t launch_poison(const Grid &g, const Fields &F, hipStream_t s)
+{
+    k_poison<<<blocks_for(g.N, 256), 256, 0, s>>>(g, F.nbr, F.f[0], F.f[1], F.phi[0], F.phi[1], F.u, F.a);
     return hipGetLastError();
 }
 

@@ -467,6 +467,7 @@ cac_status cac_set_state(cac_handle *h, const float *d_phi, const float *d_u, co
     HIPCHK(h, hipMemsetAsync(F.flag, 0, 256, h->stream));
     HIPCHK(h, launch_init(h->g, F, 0, d_u, d_pstar, h->stream));
     HIPCHK(h, launch_mass(h->g, h->t, F, F.phi[0], F.scal + 0, h->stream));
+    if (h->debug & CAC_DEBUG_POISON) HIPCHK(h, launch_poison(h->g, F, h->stream));
     h->cur = 0;
     h->steps = 0;
     h->sub = 0;
@@ -551,6 +552,16 @@ cac_status cac_set_launch(cac_handle *h, int bx, int by, int bz, int phase_tile,
     h->t = t;
     h->use_graph = use_graph != 0;
     drop_graphs(h);
+    return CAC_OK;
+}
+
+cac_status cac_set_debug(cac_handle *h, int flags)
+{
+    if (!h) return CAC_ERR_ARG;
+    if (flags & ~(CAC_DEBUG_POISON | CAC_DEBUG_REVERSE_ORDER)) return fail(h, CAC_ERR_ARG, "unknown debug flag");
+    h->debug = flags;
+    h->dp.rev_order = (flags & CAC_DEBUG_REVERSE_ORDER) ? 1 : 0;
+    drop_graphs(h);  // captured steps carry the kernel arguments
     return CAC_OK;
 }
 
@@ -672,6 +683,7 @@ cac_status cac_load_state(cac_handle *h, const void *d_buf, size_t bytes)
     HIPCHK(h, hipMemcpyAsync(h->F.pstar0, a + 32 * N, N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
     // the compressive flux is rebuilt by every ghost update; skipped wall nodes keep zero
     HIPCHK(h, hipMemsetAsync(h->F.a, 0, 3 * N * sizeof(float), h->stream));
+    if (h->debug & CAC_DEBUG_POISON) HIPCHK(h, launch_poison(h->g, h->F, h->stream));
     HIPCHK(h, hipMemsetAsync(h->F.flag, 0, 256, h->stream));
     h->cur = 0;
     h->steps = (long long)hdr[2];
