@@ -686,42 +686,46 @@ cac_status cac_batch_autotune(cac_batch *b, const char *cache_path, int trial_st
     }
     const int tiles[][3] = {{0, 256, 0}, {0, 512, 0}, {0, 128, 0}, {16, 4, 4}, {32, 4, 2}, {32, 8, 1},
                             {64, 4, 1},  {64, 2, 2},  {64, 8, 1},  {128, 2, 1}};
-    for (auto &tl : tiles) {
-        Schedule s = best;
-        s.bx = tl[0];
-        s.by = tl[1];
-        s.bz = tl[2];
-        double t;
-        if (trial(s, t) == CAC_OK && t < best_t) {
-            best_t = t;
-            best = s;
+    // two passes of the coordinate search: the second revisits the tile with
+    // the phase tile, multiplier and order the first pass chose
+    for (int pass = 0; pass < 2; ++pass) {
+        for (auto &tl : tiles) {
+            Schedule s = best;
+            s.bx = tl[0];
+            s.by = tl[1];
+            s.bz = tl[2];
+            double t;
+            if (trial(s, t) == CAC_OK && t < best_t) {
+                best_t = t;
+                best = s;
+            }
         }
-    }
-    for (int code = 1; code <= 6; ++code) {
-        Schedule s = best;
-        s.phase = code;
-        double t;
-        if (trial(s, t) == CAC_OK && t < best_t) {
-            best_t = t;
-            best = s;
+        for (int code = 1; code <= 6; ++code) {
+            Schedule s = best;
+            s.phase = code;
+            double t;
+            if (trial(s, t) == CAC_OK && t < best_t) {
+                best_t = t;
+                best = s;
+            }
         }
-    }
-    for (int m : {0, 1, 2, 4, 8}) {
-        Schedule s = best;
-        s.mult = m;
-        double t;
-        if (trial(s, t) == CAC_OK && t < best_t) {
-            best_t = t;
-            best = s;
+        for (int m : {0, 1, 2, 4, 8}) {
+            Schedule s = best;
+            s.mult = m;
+            double t;
+            if (trial(s, t) == CAC_OK && t < best_t) {
+                best_t = t;
+                best = s;
+            }
         }
-    }
-    for (int o : {0, 1}) {
-        Schedule s = best;
-        s.order = o;
-        double t;
-        if (trial(s, t) == CAC_OK && t < best_t) {
-            best_t = t;
-            best = s;
+        for (int o : {0, 1}) {
+            Schedule s = best;
+            s.order = o;
+            double t;
+            if (trial(s, t) == CAC_OK && t < best_t) {
+                best_t = t;
+                best = s;
+            }
         }
     }
     (void)hipEventDestroy(e0);
