@@ -306,8 +306,9 @@ cac_status cac_batch_set_schedule(cac_batch *b, int bx, int by, int bz, int phas
 /* Current schedule as 7 ints in the order of cac_batch_set_schedule. */
 cac_status cac_batch_get_schedule(cac_batch *b, int *out7);
 
-/* Choose the schedule by timing trial_steps steps per candidate (coordinate
- * search over the tile, the phase tile, the grid multiplier and the order).
+/* Choose the schedule by timing trial_steps steps per candidate (two passes
+ * of a coordinate search over the tile, the phase tile, the grid multiplier
+ * and the order).
  * The state is saved before and restored after.  cache_path (or NULL): JSON
  * file of schedules keyed by device and the histogram of domain shapes; a
  * matching entry is applied without timing (*best_ms = -1).  Synchronises. */
