@@ -23,10 +23,22 @@ struct AdjTape {
     int theta_cap = 0;
     std::vector<float *> ck;     // checkpoints: 27N populations, N phi (current), N phi (previous ghosts)
     int ring_K = 0;              // rings sized for this K
-    std::vector<float *> rf;     // K+1 population sets: rf[j] enters step j of the segment
-    std::vector<float *> rphi;   // K+2 phase fields: rphi[j+1] = phi with the ghosts of step j
-    std::vector<float *> ru;     // K velocities (zero on solid nodes)
-    std::vector<float *> rps;    // K fields phi* (before the correction)
+    // One or two sets of segment rings: with two, the replay of the next
+    // segment (on the auxiliary stream) runs while this one is reversed.
+    int nsets = 0;
+    std::vector<float *> rf[2];    // K+1 population sets: rf[j] enters step j of the segment
+    std::vector<float *> rphi[2];  // K+2 phase fields: rphi[j+1] = phi with the ghosts of step j
+    std::vector<float *> ru[2];    // K velocities (zero on solid nodes)
+    std::vector<float *> rps[2];   // K fields phi* (before the correction)
+    hipStream_t aux = nullptr;     // replay stream (default priority)
+    hipEvent_t ready[2] = {nullptr, nullptr}, released[2] = {nullptr, nullptr}, joined = nullptr;
+    ~AdjTape()
+    {
+        if (aux) (void)hipStreamSynchronize(aux);
+        for (hipEvent_t e : {ready[0], ready[1], released[0], released[1], joined})
+            if (e) (void)hipEventDestroy(e);
+        if (aux) (void)hipStreamDestroy(aux);
+    }
     // reverse state
     bool adj_ready = false;
     float *mb[2] = {nullptr, nullptr}, *pb[2] = {nullptr, nullptr};
@@ -67,31 +79,58 @@ bool alloc_n(cac_handle *h, T *&p, size_t n)
     return p != nullptr;
 }
 
+// One set of segment rings; false when the device memory is not there.
+bool alloc_ring_set(cac_handle *h, AdjTape &T, int k)
+{
+    const size_t N = h->g.N;
+    const int K = T.K;
+    while ((int)T.rf[k].size() < K + 1) {
+        float *p;
+        if (!alloc_n(h, p, 27 * N)) return false;
+        T.rf[k].push_back(p);
+    }
+    while ((int)T.rphi[k].size() < K + 2) {
+        float *p;
+        if (!alloc_n(h, p, N)) return false;
+        T.rphi[k].push_back(p);
+    }
+    while ((int)T.ru[k].size() < K) {
+        float *p;
+        if (!alloc_n(h, p, 3 * N)) return false;
+        // the collision never writes solid nodes: keep their velocity at zero
+        if (hipMemsetAsync(p, 0, 3 * N * sizeof(float), h->stream) != hipSuccess) return false;
+        T.ru[k].push_back(p);
+    }
+    while ((int)T.rps[k].size() < K) {
+        float *p;
+        if (!alloc_n(h, p, N)) return false;
+        T.rps[k].push_back(p);
+    }
+    return true;
+}
+
 cac_status ensure_rings(cac_handle *h, AdjTape &T)
 {
     const size_t N = h->g.N;
     const int K = T.K;
-    while ((int)T.rf.size() < K + 1) {
-        float *p;
-        if (!alloc_n(h, p, 27 * N)) return fail(h, CAC_ERR_ALLOC, "adjoint ring");
-        T.rf.push_back(p);
+    if (!alloc_ring_set(h, T, 0)) return fail(h, CAC_ERR_ALLOC, "adjoint ring");
+    // a second set (for the overlapped replay) only with room to spare
+    bool two = (int)T.rf[1].size() >= K + 1 && (int)T.rphi[1].size() >= K + 2 && (int)T.ru[1].size() >= K &&
+               (int)T.rps[1].size() >= K;
+    if (!two) {
+        size_t free_b = 0, total_b = 0;
+        const size_t set_b = ((size_t)(K + 1) * 27 + (size_t)(K + 2) + (size_t)K * 4) * N * sizeof(float);
+        two = hipMemGetInfo(&free_b, &total_b) == hipSuccess && 2 * set_b < free_b && alloc_ring_set(h, T, 1);
     }
-    while ((int)T.rphi.size() < K + 2) {
-        float *p;
-        if (!alloc_n(h, p, N)) return fail(h, CAC_ERR_ALLOC, "adjoint ring");
-        T.rphi.push_back(p);
-    }
-    while ((int)T.ru.size() < K) {
-        float *p;
-        if (!alloc_n(h, p, 3 * N)) return fail(h, CAC_ERR_ALLOC, "adjoint ring");
-        // the collision never writes solid nodes: keep their velocity at zero
-        HIPCHK(h, hipMemsetAsync(p, 0, 3 * N * sizeof(float), h->stream));
-        T.ru.push_back(p);
-    }
-    while ((int)T.rps.size() < K) {
-        float *p;
-        if (!alloc_n(h, p, N)) return fail(h, CAC_ERR_ALLOC, "adjoint ring");
-        T.rps.push_back(p);
+    T.nsets = two ? 2 : 1;
+    if (T.nsets == 2 && !T.aux) {
+        if (hipStreamCreateWithFlags(&T.aux, hipStreamNonBlocking) != hipSuccess) {
+            T.aux = nullptr;
+            T.nsets = 1;
+        } else {
+            for (hipEvent_t *e : {&T.ready[0], &T.ready[1], &T.released[0], &T.released[1], &T.joined})
+                HIPCHK(h, hipEventCreateWithFlags(e, hipEventDisableTiming));
+        }
     }
     if (!T.adj_ready) {
         bool ok = alloc_n(h, T.mb[0], 10 * N) && alloc_n(h, T.mb[1], 10 * N) && alloc_n(h, T.pb[0], N) &&
@@ -131,33 +170,53 @@ cac_status ensure_tables(cac_handle *h, AdjTape &T)
     return CAC_OK;
 }
 
-// Forward step j of the current segment, keeping its state in the rings.
-cac_status replay_step(cac_handle *h, AdjTape &T, int j)
+// Forward step j of a segment on stream st, keeping its state in ring set k.
+// Only the replay touches the handle's compressive flux, tile partials and
+// volume scalars (the reverse step reads the target volume alone).
+cac_status replay_step(cac_handle *h, AdjTape &T, int k, int j, hipStream_t st)
 {
     Fields F = h->F;
     F.theta = T.theta;
-    F.phi[0] = T.rphi[j + 1];
-    F.phi[1] = T.rphi[j];
-    HIPCHK(h, launch_ghost(h->g, h->dp, F, 0, h->stream));
-    F.f[0] = T.rf[j];
-    F.f[1] = T.rf[j + 1];
-    F.u = T.ru[j];
-    HIPCHK(h, launch_hydro(h->g, h->t, h->dp, F, 0, 0, h->stream));
-    F.phi[1] = T.rps[j];
-    HIPCHK(h, launch_phase(h->g, h->t, h->dp, F, 0, h->stream));
-    HIPCHK(h, launch_volume_copy(h->g, h->t, h->dp, F, T.rps[j], T.rphi[j + 1], T.rphi[j + 2], h->stream));
+    F.phi[0] = T.rphi[k][j + 1];
+    F.phi[1] = T.rphi[k][j];
+    HIPCHK(h, launch_ghost(h->g, h->dp, F, 0, st));
+    F.f[0] = T.rf[k][j];
+    F.f[1] = T.rf[k][j + 1];
+    F.u = T.ru[k][j];
+    HIPCHK(h, launch_hydro(h->g, h->t, h->dp, F, 0, 0, st));
+    F.phi[1] = T.rps[k][j];
+    HIPCHK(h, launch_phase(h->g, h->t, h->dp, F, 0, st));
+    HIPCHK(h, launch_volume_copy(h->g, h->t, h->dp, F, T.rps[k][j], T.rphi[k][j + 1], T.rphi[k][j + 2], st));
     return CAC_OK;
 }
 
-// Reverse of step j of the current segment; cotangents move from parity c to c ^ 1.
-cac_status reverse_step(cac_handle *h, AdjTape &T, int j, int c)
+// Replay of segment seg (from its checkpoint) into ring set k on stream st.
+cac_status replay_segment(cac_handle *h, AdjTape &T, int seg, int k, hipStream_t st)
+{
+    const size_t N = h->g.N;
+    const int n0 = seg * T.K;
+    const int L = std::min(T.K, T.nsteps - n0);
+    const float *ck = T.ck[seg];
+    HIPCHK(h, hipMemcpyAsync(T.rf[k][0], ck, 27 * N * sizeof(float), hipMemcpyDeviceToDevice, st));
+    HIPCHK(h, hipMemcpyAsync(T.rphi[k][1], ck + 27 * N, N * sizeof(float), hipMemcpyDeviceToDevice, st));
+    HIPCHK(h, hipMemcpyAsync(T.rphi[k][0], ck + 28 * N, N * sizeof(float), hipMemcpyDeviceToDevice, st));
+    for (int j = 0; j < L; ++j) {
+        cac_status s = replay_step(h, T, k, j, st);
+        if (s != CAC_OK) return s;
+    }
+    return CAC_OK;
+}
+
+// Reverse of step j of a segment held in ring set k; cotangents move from
+// parity c to c ^ 1.
+cac_status reverse_step(cac_handle *h, AdjTape &T, int k, int j, int c)
 {
     AdjStep S{};
-    S.fprev = T.rf[j];
-    S.phihat = T.rphi[j + 1];
-    S.phiold = T.rphi[j];
-    S.u = T.ru[j];
-    S.phistar = T.rps[j];
+    S.fprev = T.rf[k][j];
+    S.phihat = T.rphi[k][j + 1];
+    S.phiold = T.rphi[k][j];
+    S.u = T.ru[k][j];
+    S.phistar = T.rps[k][j];
     S.pb_in = T.pb[c];
     S.mb_in = T.mb[c];
     S.pb_out = T.pb[c ^ 1];
@@ -257,22 +316,44 @@ cac_status cac_tape_backward(cac_handle *h, const float *d_phibar, double *d_dth
     HIPCHK(h, hipMemsetAsync(T.rs, 0, 4 * sizeof(double), h->stream));
     int c = 0;
     const int nck = (T.nsteps + T.K - 1) / T.K;
+    // Segments are reversed from the last to the first.  With two ring sets
+    // the replay of segment seg - 1 (auxiliary stream, set k ^ 1) overlaps the
+    // reverse of segment seg (handle stream, set k); events order each replay
+    // after the reverse that last used its set, and each reverse after its
+    // replay.  With one set the two alternate on the handle stream.
+    const bool overlap = T.nsets == 2;
+    if (overlap) {
+        HIPCHK(h, hipEventRecord(T.joined, h->stream));  // the aux stream starts after everything queued so far
+        HIPCHK(h, hipStreamWaitEvent(T.aux, T.joined, 0));
+        st = replay_segment(h, T, nck - 1, 0, T.aux);
+        if (st != CAC_OK) return st;
+        HIPCHK(h, hipEventRecord(T.ready[0], T.aux));
+    }
     for (int seg = nck - 1; seg >= 0; --seg) {
-        const int n0 = seg * T.K;
-        const int L = std::min(T.K, T.nsteps - n0);
-        const float *ck = T.ck[seg];
-        HIPCHK(h, hipMemcpyAsync(T.rf[0], ck, 27 * N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
-        HIPCHK(h, hipMemcpyAsync(T.rphi[1], ck + 27 * N, N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
-        HIPCHK(h, hipMemcpyAsync(T.rphi[0], ck + 28 * N, N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
-        for (int j = 0; j < L; ++j) {
-            st = replay_step(h, T, j);
+        const int L = std::min(T.K, T.nsteps - seg * T.K);
+        const int k = overlap ? (nck - 1 - seg) & 1 : 0;
+        if (overlap) {
+            if (seg > 0) {
+                if (seg + 1 <= nck - 1) HIPCHK(h, hipStreamWaitEvent(T.aux, T.released[k ^ 1], 0));
+                st = replay_segment(h, T, seg - 1, k ^ 1, T.aux);
+                if (st != CAC_OK) return st;
+                HIPCHK(h, hipEventRecord(T.ready[k ^ 1], T.aux));
+            }
+            HIPCHK(h, hipStreamWaitEvent(h->stream, T.ready[k], 0));
+        } else {
+            st = replay_segment(h, T, seg, 0, h->stream);
             if (st != CAC_OK) return st;
         }
         for (int j = L - 1; j >= 0; --j) {
-            st = reverse_step(h, T, j, c);
+            st = reverse_step(h, T, k, j, c);
             if (st != CAC_OK) return st;
             c ^= 1;
         }
+        if (overlap) HIPCHK(h, hipEventRecord(T.released[k], h->stream));
+    }
+    if (overlap) {
+        HIPCHK(h, hipEventRecord(T.joined, T.aux));  // nothing on the aux stream outlives this call
+        HIPCHK(h, hipStreamWaitEvent(h->stream, T.joined, 0));
     }
     if (nwall)
         HIPCHK(h, hipMemcpyAsync(d_dtheta, T.thb, nwall * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
