@@ -20,7 +20,10 @@
  * here is W -> H -> P -> V, all explicit at time level n):
  *   W  ghost update at boundary solid nodes (Sec. II B, Eqs. (36)-(47)),
  *      Jacobi: donor gradients read the previous ghosts;
- *   H  hydrodynamic collide + stream (Sec. II A, Eqs. (3)-(23));
+ *   H  hydrodynamic collide + stream (Sec. II A, Eqs. (3)-(23)); the
+ *      non-equilibrium moment A2 of Eq. (14) is either the local second
+ *      moment of the node's populations (collision = 0) or the gradient form
+ *      of Eq. (15) from the velocity field (collision = 1);
  *   P  CAC finite-difference update (Sec. II A 1, Eqs. (24)-(35));
  *   V  global volume correction (Sec. II C, Eqs. (48)-(55)).
  *
@@ -52,6 +55,9 @@ typedef struct {
     int volume_correction;           /* 1: apply Eq. (53) every step */
     int wall_compression;            /* compressive flux a at wall nodes: 0 -> a = 0,
                                       * 1 -> a = g (1 - g) grad(phi)_c / |grad(phi)_c| */
+    int collision;                   /* non-equilibrium moment A2 of Eq. (14): 0 -> local second
+                                      * moment of the pre-collision populations; 1 -> gradient
+                                      * form of Eq. (15) from the velocity field */
 } orc_params;
 
 /* ------------------------------------------------------------------ */
@@ -192,19 +198,17 @@ void orc_fneq_reg(const double u[3], const double A2[9], double out[Q])
     }
 }
 
-/* Collision at one fluid node (Sec. II A).  Inputs: pre-collision populations
- * f, local phase field phi with its isotropic gradient G and Laplacian L.
- * Outputs: post-collision populations, velocity u (Eq. (7)) and p* (Eq. (6)).
+/* Macroscopic part of the collision at one fluid node (Sec. II A).  Inputs:
+ * pre-collision populations f, local phase field phi with its isotropic
+ * gradient G and Laplacian L.  Outputs: p* (Eq. (6)), velocity u (Eq. (7)),
+ * acceleration a = F/rho of the total force (Eq. (18)) and omega (Eq. (10)).
  *
  * Readings where the paper is silent:
  *  - forces enter S_i and u as accelerations a = F/rho;
- *  - the non-equilibrium moment A2 is the local second moment of
- *    f - (f^eq - S/2), i.e. of f minus the shifted equilibrium of the
- *    trapezoidal forcing (text after Eq. (17));
  *  - F_nu (Eq. (21)) uses the equilibrium at u' = j + a'/2 built without F_nu;
  *  - F_ext = (rho(phi) - rho_g) g. */
-void orc_collide_node(const orc_params *p, double phi, const double G[3], double L, const double f[Q],
-                      double fpost[Q], double u_out[3], double *pstar_out)
+void orc_macro_node(const orc_params *p, double phi, const double G[3], double L, const double f[Q],
+                    double *pstar_out, double u_out[3], double a_out[3], double *omega_out)
 {
     /* chemical potential and capillary force, Eq. (19) and the definition after it:
      * mu_phi = 4 beta (phi - phi_l)(phi - phi_g)(phi - phi_0) - kappa_phi lap(phi),
@@ -245,31 +249,55 @@ void orc_collide_node(const orc_params *p, double phi, const double G[3], double
     for (int i = 0; i < Q; ++i)
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) Pi[a][b] += (f[i] - feq1[i]) * CV[i][a] * CV[i][b];
-    double a[3], u[3];
     for (int d = 0; d < 3; ++d) {
         double Fnu = 0.0;
         for (int b = 0; b < 3; ++b) Fnu += Pi[d][b] * grad_rho[b];
         Fnu *= -nu * omega / CS2;
-        a[d] = a1[d] + Fnu / rho;
-        u[d] = j[d] + 0.5 * a[d]; /* Eq. (7) */
+        a_out[d] = a1[d] + Fnu / rho;
+        u_out[d] = j[d] + 0.5 * a_out[d]; /* Eq. (7) */
     }
+    *pstar_out = ps;
+    *omega_out = omega;
+}
 
-    /* equilibrium, forcing and regularised non-equilibrium, Eqs. (11), (14), (17) */
-    double feq[Q], S[Q], fneq[Q], A2[9] = {0};
-    orc_feq(ps, u, feq);
+/* Local non-equilibrium moment (reading of Eq. (14)): the second moment of
+ * f - (f^eq - S/2), f minus the shifted equilibrium of the trapezoidal
+ * forcing (text after Eq. (17)).  A2 is a full 3x3 row-major tensor. */
+void orc_a2_local(double pstar, const double u[3], const double a[3], const double f[Q], double A2[9])
+{
+    double feq[Q], S[Q];
+    orc_feq(pstar, u, feq);
     orc_guo(u, a, S);
+    for (int k = 0; k < 9; ++k) A2[k] = 0.0;
     for (int i = 0; i < Q; ++i)
         for (int al = 0; al < 3; ++al)
             for (int be = 0; be < 3; ++be)
                 A2[3 * al + be] += (f[i] - feq[i] + 0.5 * S[i]) * CV[i][al] * CV[i][be];
+}
+
+/* Post-collision populations from the macroscopic fields and a
+ * non-equilibrium moment A2: Eq. (3) with f^eq <- f^eq - S/2 (text after
+ * Eq. (17)) and the regularised f^neq of Eqs. (14), (16):
+ *   f_post = f^eq - S/2 + S + (1 - omega) f^neq_reg */
+void orc_post_node(double pstar, const double u[3], const double a[3], double omega, const double A2[9],
+                   double fpost[Q])
+{
+    double feq[Q], S[Q], fneq[Q];
+    orc_feq(pstar, u, feq);
+    orc_guo(u, a, S);
     orc_fneq_reg(u, A2, fneq);
-
-    /* Eq. (3) with f^eq <- f^eq - S/2 and the regularised f^neq:
-     * f_post = f^eq - S/2 + S + (1 - omega) f^neq_reg */
     for (int i = 0; i < Q; ++i) fpost[i] = feq[i] + 0.5 * S[i] + (1.0 - omega) * fneq[i];
+}
 
-    for (int d = 0; d < 3; ++d) u_out[d] = u[d];
-    *pstar_out = ps;
+/* Collision at one fluid node with the local non-equilibrium moment
+ * (collision = 0).  Outputs: post-collision populations, u and p*. */
+void orc_collide_node(const orc_params *p, double phi, const double G[3], double L, const double f[Q],
+                      double fpost[Q], double u_out[3], double *pstar_out)
+{
+    double a[3], omega, A2[9];
+    orc_macro_node(p, phi, G, L, f, pstar_out, u_out, a, &omega);
+    orc_a2_local(*pstar_out, u_out, a, f, A2);
+    orc_post_node(*pstar_out, u_out, a, omega, A2, fpost);
 }
 
 /* ------------------------------------------------------------------ */
@@ -472,10 +500,43 @@ int orc_ghost(const orc_params *p, int nx, int ny, int nz, const uint8_t *solid,
 /* ------------------------------------------------------------------ */
 /* Substep H: hydrodynamics (Sec. II A)                                 */
 
+/* Gradient form of the non-equilibrium moment, Eq. (15), at every fluid node:
+ *   A2_ab = -(c_s^2/omega) (d_a u_b + d_b u_a),
+ * with the velocity derivatives taken by the isotropic gradient of Eq. (22)
+ * applied to each velocity component.  Reading: u = 0 on solid nodes (the
+ * walls are at rest).  u: 3 planes of N; omega: N; A2: 9 planes of N
+ * (row-major a, b), zero on solid nodes. */
+void orc_a2grad(int nx, int ny, int nz, const uint8_t *solid, const double *u, const double *omega, double *A2)
+{
+    dims_t g = {nx, ny, nz, (long)nx * ny * nz};
+    const long N = g.N;
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; ++n) {
+        for (int k = 0; k < 9; ++k) A2[k * N + n] = 0.0;
+        if (solid[n]) continue;
+        double D[3][3] = {{0}}; /* D[b][a] = d_b u_a */
+        for (int i = 0; i < Q; ++i) {
+            long y = neighbour(&g, n, i);
+            if (solid[y]) continue;
+            for (int b = 0; b < 3; ++b)
+                for (int a = 0; a < 3; ++a) D[b][a] += weight(i) * CV[i][b] * u[a * N + y] / CS2;
+        }
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) A2[(3 * a + b) * N + n] = -(CS2 / omega[n]) * (D[a][b] + D[b][a]);
+    }
+}
+
 /* f_in: pre-collision populations on fluid nodes.  Writes the post-collision
  * populations (fpost, optional), the streamed populations f_out (pull with
  * halfway bounce-back: f_out_i(x) = fpost_i(x - c_i) if that node is fluid,
- * else fpost_opp(i)(x)), and u, p* on fluid nodes. */
+ * else fpost_opp(i)(x)), and u, p* on fluid nodes.
+ *
+ * collision = 0: A2 is the local moment of each node's own populations.
+ * collision = 1: the macroscopic fields of every node come first; A2 is then
+ * the gradient form of Eq. (15) built from the new velocity field, and the
+ * post-collision populations are assembled from p*, u, a, omega and that A2
+ * (the thread-safe formulation of Sec. II A: both parts of the populations
+ * follow from macroscopic quantities). */
 int orc_hydro(const orc_params *p, int nx, int ny, int nz, const uint8_t *solid, const double *phi_hat,
               const double *f_in, double *fpost_out, double *f_out, double *u, double *pstar)
 {
@@ -483,17 +544,56 @@ int orc_hydro(const orc_params *p, int nx, int ny, int nz, const uint8_t *solid,
     const long N = g.N;
     double *fpost = fpost_out ? fpost_out : malloc(sizeof(double) * Q * N);
     if (!fpost) return -1;
+    if (p->collision == 1) {
+        double *acc = malloc(sizeof(double) * 3 * N), *om = malloc(sizeof(double) * N);
+        double *A2 = malloc(sizeof(double) * 9 * N), *uf = calloc(3 * N, sizeof(double));
+        if (!acc || !om || !A2 || !uf) return -1;
 #pragma omp parallel for schedule(static)
-    for (long n = 0; n < N; ++n) {
-        if (solid[n]) continue;
-        double G[3], f[Q], fp[Q], uu[3], ps;
-        grad_iso_at(&g, phi_hat, n, G);
-        double L = lap_iso_at(&g, phi_hat, n);
-        for (int i = 0; i < Q; ++i) f[i] = f_in[i * N + n];
-        orc_collide_node(p, phi_hat[n], G, L, f, fp, uu, &ps);
-        for (int i = 0; i < Q; ++i) fpost[i * N + n] = fp[i];
-        for (int d = 0; d < 3; ++d) u[d * N + n] = uu[d];
-        pstar[n] = ps;
+        for (long n = 0; n < N; ++n) {
+            om[n] = 1.0;
+            if (solid[n]) continue;
+            double G[3], f[Q], uu[3], aa[3], ps;
+            grad_iso_at(&g, phi_hat, n, G);
+            double L = lap_iso_at(&g, phi_hat, n);
+            for (int i = 0; i < Q; ++i) f[i] = f_in[i * N + n];
+            orc_macro_node(p, phi_hat[n], G, L, f, &ps, uu, aa, &om[n]);
+            for (int d = 0; d < 3; ++d) {
+                uf[d * N + n] = uu[d];
+                acc[d * N + n] = aa[d];
+                u[d * N + n] = uu[d];
+            }
+            pstar[n] = ps;
+        }
+        orc_a2grad(nx, ny, nz, solid, uf, om, A2);
+#pragma omp parallel for schedule(static)
+        for (long n = 0; n < N; ++n) {
+            if (solid[n]) continue;
+            double uu[3], aa[3], A[9], fp[Q];
+            for (int d = 0; d < 3; ++d) {
+                uu[d] = uf[d * N + n];
+                aa[d] = acc[d * N + n];
+            }
+            for (int k = 0; k < 9; ++k) A[k] = A2[k * N + n];
+            orc_post_node(pstar[n], uu, aa, om[n], A, fp);
+            for (int i = 0; i < Q; ++i) fpost[i * N + n] = fp[i];
+        }
+        free(acc);
+        free(om);
+        free(A2);
+        free(uf);
+    } else {
+#pragma omp parallel for schedule(static)
+        for (long n = 0; n < N; ++n) {
+            if (solid[n]) continue;
+            double G[3], f[Q], fp[Q], uu[3], ps;
+            grad_iso_at(&g, phi_hat, n, G);
+            double L = lap_iso_at(&g, phi_hat, n);
+            for (int i = 0; i < Q; ++i) f[i] = f_in[i * N + n];
+            orc_collide_node(p, phi_hat[n], G, L, f, fp, uu, &ps);
+            for (int i = 0; i < Q; ++i) fpost[i * N + n] = fp[i];
+            for (int d = 0; d < 3; ++d) u[d * N + n] = uu[d];
+            pstar[n] = ps;
+        }
     }
 #pragma omp parallel for schedule(static)
     for (long n = 0; n < N; ++n) {

@@ -35,7 +35,8 @@ class OrcParams(C.Structure):
     _fields_ = [("rho_l", C.c_double), ("rho_g", C.c_double), ("nu_l", C.c_double), ("nu_g", C.c_double),
                 ("sigma", C.c_double), ("delta", C.c_double), ("D", C.c_double), ("g", C.c_double * 3),
                 ("eps_phi", C.c_double), ("eps_n", C.c_double), ("sin_tol", C.c_double),
-                ("cot_max", C.c_double), ("volume_correction", C.c_int), ("wall_compression", C.c_int)]
+                ("cot_max", C.c_double), ("volume_correction", C.c_int), ("wall_compression", C.c_int),
+                ("collision", C.c_int)]
 
 
 @dataclass
@@ -55,6 +56,7 @@ class Params:
     cot_max: float = 1e6
     volume_correction: int = 1
     wall_compression: int = 1
+    collision: int = 0          # A2 of Eq. (14): 0 local second moment, 1 gradient form of Eq. (15)
 
     def c_struct(self) -> OrcParams:
         p = OrcParams()
@@ -65,6 +67,7 @@ class Params:
             p.g[d] = float(self.g[d])
         p.volume_correction = int(self.volume_correction)
         p.wall_compression = int(self.wall_compression)
+        p.collision = int(self.collision)
         return p
 
 
@@ -85,6 +88,10 @@ def lib():
         L.orc_guo.argtypes = [dp, dp, dp]
         L.orc_fneq_reg.argtypes = [dp, dp, dp]
         L.orc_collide_node.argtypes = [pp, C.c_double, dp, C.c_double, dp, dp, dp, dp]
+        L.orc_macro_node.argtypes = [pp, C.c_double, dp, C.c_double, dp, dp, dp, dp, dp]
+        L.orc_a2_local.argtypes = [C.c_double, dp, dp, dp, dp]
+        L.orc_post_node.argtypes = [C.c_double, dp, dp, C.c_double, dp, dp]
+        L.orc_a2grad.argtypes = [C.c_int, C.c_int, C.c_int, u8p, dp, dp, dp]
         L.orc_grad_iso.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp]
         L.orc_lap_iso.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp]
         L.orc_wall_nodes.argtypes = [C.c_int, C.c_int, C.c_int, u8p, i32p, i32p, i32p, C.c_int]
@@ -212,6 +219,18 @@ def hydro(params, shape, solid, phi_hat, f_in):
     p = params.c_struct()
     lib().orc_hydro(C.byref(p), nx, ny, nz, _u8(solid), _d(phi_hat), _d(f_in), _d(fpost), _d(fout), _d(u), _d(ps))
     return fpost, fout, u, ps
+
+
+def a2grad(shape, solid, u, omega):
+    """Gradient form of the non-equilibrium moment, Eq. (15), at every fluid
+    node (u = 0 on solid nodes): returns 9 planes of N, row-major (a, b)."""
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    solid = np.ascontiguousarray(solid, dtype=np.uint8).reshape(-1)
+    u, omega = _f64(u).reshape(-1), _f64(omega).reshape(-1)
+    out = np.zeros(9 * N)
+    lib().orc_a2grad(nx, ny, nz, _u8(solid), _d(u), _d(omega), _d(out))
+    return out
 
 
 def phase(params, shape, solid, phi_hat, u, a_wall=None):

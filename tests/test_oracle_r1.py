@@ -1,0 +1,157 @@
+"""Pins of the oracle's gradient-form collision (collision = 1).
+
+The non-equilibrium moment of the regularised populations, Eq. (14), is taken in
+the gradient form of Eq. (15), A2 = -(c_s^2/omega)(grad u + grad u^T), with the
+velocity derivatives from the isotropic stencil of Eq. (22) and u = 0 on solid
+nodes.  Pinned here against:
+* closed forms of the stencil on sinusoidal velocity fields (the isotropic
+  derivative of sin(kx) is sin(k) cos(kx)) and on a uniform flow beside a wall;
+* the decay of a shear wave, which must tend to nu k^2 with
+  nu = c_s^2 (1/omega - 1/2), Eq. (4), at second order in k;
+* invariants: a uniform flow stays uniform; the fluid sum of p* is conserved;
+* the independent whole-array implementation in oracle/literal.py.
+"""
+import numpy as np
+import pytest
+
+import oracle.oracle as O
+
+CS2 = 1.0 / 3.0
+
+
+def _omega_field(N, seed=0):
+    return np.random.default_rng(seed).uniform(0.6, 1.9, N)
+
+
+@pytest.mark.parametrize("a,b", [(0, 1), (1, 0), (0, 2), (2, 0), (1, 2), (2, 1), (0, 0), (1, 1), (2, 2)])
+def test_a2grad_sinusoid_closed_form(a, b):
+    # u_a = U sin(k x_b): d_b u_a = U sin(k) cos(k x_b) exactly on the D3Q27 stencil
+    shape = (12, 10, 8)
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    L = shape[b]
+    k = 2.0 * np.pi / L
+    U = 0.03
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    xb = (x, y, z)[b]
+    u = np.zeros((3, nz, ny, nx))
+    u[a] = U * np.sin(k * xb)
+    om = _omega_field(N)
+    A2 = O.a2grad(shape, np.zeros(N, np.uint8), u.reshape(-1), om).reshape(3, 3, N)
+    d = (U * np.sin(k) * np.cos(k * xb)).reshape(-1)
+    want = np.zeros((3, 3, N))
+    want[a, b] += -(CS2 / om) * d
+    want[b, a] += -(CS2 / om) * d
+    np.testing.assert_allclose(A2, want, rtol=0, atol=1e-15)
+
+
+def test_a2grad_uniform_flow_beside_a_wall():
+    # u = (U, 0, 0) on fluid nodes, solid layer z = 0 (u = 0 there): next to the
+    # wall d_z u_x = (u(z+1) - u(z-1))/2 = +U/2 at z = 1 and -U/2 at z = nz - 1
+    shape = (6, 5, 7)
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    solid = np.zeros((nz, ny, nx), np.uint8)
+    solid[0] = 1
+    U = 0.02
+    u = np.zeros((3, nz, ny, nx))
+    u[0] = np.where(solid == 0, U, 0.0)
+    om = _omega_field(N, 1)
+    A2 = O.a2grad(shape, solid.reshape(-1), u.reshape(-1), om).reshape(3, 3, nz, ny, nx)
+    om3 = om.reshape(nz, ny, nx)
+    dz = np.zeros((nz, ny, nx))
+    dz[1] = U / 2
+    dz[nz - 1] = -U / 2
+    want = np.zeros((3, 3, nz, ny, nx))
+    want[0, 2] = want[2, 0] = np.where(solid == 0, -(CS2 / om3) * dz, 0.0)
+    np.testing.assert_allclose(A2, want, rtol=0, atol=1e-16)
+
+
+def _shear_rate(collision, L, nu=0.04, U=1e-3, t1=50, t2=250):
+    shape = (2, L, 2)
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    k = 2.0 * np.pi / L
+    y = np.arange(L)
+    u0 = np.zeros((3, nz, ny, nx))
+    u0[0] = U * np.sin(k * y)[None, :, None]
+    prm = O.Params(nu_l=nu, nu_g=nu, collision=collision)
+    s = O.OracleSim.create(shape, np.zeros(N, np.uint8), np.full(N, np.pi / 2), prm, np.ones(N), u0=u0.reshape(-1))
+
+    def amp():
+        prof = s.u.reshape(3, nz, ny, nx)[0].mean(axis=(0, 2))
+        return 2.0 / L * np.sum(prof * np.sin(k * y))
+
+    s.step(t1)
+    a1 = amp()
+    s.step(t2 - t1)
+    a2 = amp()
+    return np.log(a1 / a2) / (t2 - t1) / (nu * k * k) - 1.0
+
+
+def test_shear_wave_decays_at_nu_k2_second_order():
+    e32, e64 = _shear_rate(1, 32), _shear_rate(1, 64)
+    assert abs(e32) < 4e-2 and abs(e64) < 1e-2, (e32, e64)
+    assert 3.0 < e32 / e64 < 5.0, (e32, e64)  # second order in k
+    # the local-moment collision converges to the same rate
+    r32, r64 = _shear_rate(0, 32), _shear_rate(0, 64)
+    assert abs(r32) < 4e-3 and abs(r64) < 1e-3 and 3.0 < r32 / r64 < 5.0, (r32, r64)
+
+
+@pytest.mark.parametrize("phi_c", [1.0, 0.3])
+def test_uniform_flow_stays_uniform(phi_c):
+    shape = (6, 5, 4)
+    N = 6 * 5 * 4
+    u0 = np.zeros((3, N))
+    u0[0], u0[1], u0[2] = 0.02, -0.01, 0.015
+    prm = O.Params(rho_l=5.0, rho_g=1.0, nu_l=0.02, nu_g=0.1, collision=1)
+    s = O.OracleSim.create(shape, np.zeros(N, np.uint8), np.full(N, np.pi / 2), prm, np.full(N, phi_c),
+                           pstar0=np.full(N, 0.01), u0=u0.reshape(-1))
+    s.step(20)
+    np.testing.assert_allclose(s.u.reshape(3, N), u0, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(s.pstar, 0.01, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(s.phi, phi_c, rtol=0, atol=1e-14)
+
+
+def _wall_case():
+    from paper_2607_25444_amd import workloads as W
+    shape = (10, 9, 8)
+    nx, ny, nz = shape
+    solid = np.zeros((nz, ny, nx), np.uint8)
+    solid[0] = 1
+    solid[3:5, 4, 5:7] = 1
+    phi0 = W.tanh_droplet(shape, (4.6, 4.3, 1.5), 3.0, 3.0).reshape(-1)
+    theta = np.deg2rad(np.random.default_rng(3).uniform(40, 140, nx * ny * nz))
+    prm = dict(rho_l=10.0, rho_g=1.0, nu_l=0.05, nu_g=0.1, sigma=0.01, delta=3.0, D=0.1, g=(0.0, 0.0, -1e-5),
+               eps_phi=1e-3, eps_n=1e-12, sin_tol=1e-6, cot_max=1e6, volume_correction=1, wall_compression=1,
+               collision=1)
+    return shape, solid, phi0, theta, prm
+
+
+def test_pstar_sum_is_conserved():
+    shape, solid, phi0, theta, prm = _wall_case()
+    s = O.OracleSim.create(shape, solid.reshape(-1), theta, O.Params(**prm), phi0)
+    fl = solid.reshape(-1) == 0
+    s.step(1)
+    m1 = s.pstar[fl].sum()
+    s.step(10)
+    assert abs(np.abs(s.u).max()) > 1e-5
+    assert abs(s.pstar[fl].sum() - m1) < 1e-13
+
+
+def test_c_oracle_matches_literal():
+    torch = pytest.importorskip("torch")  # noqa: F841
+    from oracle import literal as Lt
+    shape, solid, phi0, theta, prm = _wall_case()
+    s = O.OracleSim.create(shape, solid.reshape(-1), theta, O.Params(**prm), phi0)
+    s.step(6)
+    lit = Lt.LiteralSim(shape, solid, prm, phi0)
+    lit.step(lit.wall_theta_from_field(theta), 6)
+    np.testing.assert_allclose(s.phi, lit.phi.numpy().reshape(-1), rtol=0, atol=1e-13)
+    np.testing.assert_allclose(s.u, lit.u.numpy().reshape(-1), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(s.pstar, lit.pstar.numpy().reshape(-1), rtol=0, atol=1e-14)
+    # and the two collisions are different schemes
+    prm0 = dict(prm, collision=0)
+    s0 = O.OracleSim.create(shape, solid.reshape(-1), theta, O.Params(**prm0), phi0)
+    s0.step(6)
+    assert np.abs(s0.u - s.u).max() > 1e-2 * np.abs(s0.u).max()
