@@ -156,6 +156,45 @@ def bench_batch(torch, capi, W, steps, warmup, seed, singles=True, tune_cache=No
     return out
 
 
+# Gradient-form hydrodynamic substep (two kernels): coefficient pass reads the
+# record (p*, a, omega: 20 B) and the velocity (12 B) and writes 17 Hermite
+# coefficients (68 B); the stream pass reads the coefficients (68 B) and phi
+# (4 B) and writes the record (20 B) and the velocity (12 B).
+R1_HYDRO_BYTES_PER_LU = (5 + 3 + 17) * 4 + (17 + 1 + 5 + 3) * 4
+
+
+def bench_r1(torch, capi, w, launch, steps, warmup):
+    """The same workload with the gradient-form collision (collision = 1: no
+    populations stored, Eq. (15) from the velocity field), timed like the plain
+    step."""
+    prm = dict(w.params)
+    prm["collision"] = 1
+    sim = capi.Sim(w.shape, prm)
+    sim.set_launch(*launch)
+    sim.set_geometry(w.solid, w.theta)
+    sim.set_state(w.phi0, w.meta.get("u0"))
+    sim.step(warmup)
+    sim.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(sim.stream)
+    sim.step(steps)
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    sim.sync()
+    kp = min(steps, 100)
+    kavg = [v / kp for v in sim.profile_step(kp)]
+    sim.close()
+    achieved = w.n_fluid * R1_HYDRO_BYTES_PER_LU / (kavg[1] * 1e-3) / 1e9
+    return {"path": "collision = 1 (gradient-form A2, moment-only state)", "steps": steps,
+            "ms_per_step": round(ms, 5), "value": round(w.n_fluid / (ms * 1e-3) / 1e6, 2), "unit": "MLUPS",
+            "kernel_ms": {"W": round(kavg[0], 5), "H": round(kavg[1], 5), "P": round(kavg[2], 5),
+                          "V": round(kavg[3], 5)},
+            "hydro_bytes_per_lu": R1_HYDRO_BYTES_PER_LU, "hydro_algorithmic_GBs": round(achieved, 1),
+            "hydro_frac_of_peak": round(achieved / HBM_PEAK_GBS, 4)}
+
+
 def bench_adjoint(torch, capi, tuning, W, steps, K, seed):
     """Reverse-mode sweep on the contact-angle inversion workload (128 x 128 x 64,
     bump angle field): cac_tape_forward (steps, checkpoints every K) + loss +
@@ -238,6 +277,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=1000)
     ap.add_argument("--adjoint-K", type=int, default=50)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--r1-steps", type=int, default=200)
+    ap.add_argument("--no-r1", action="store_true", help="skip the gradient-form collision (collision = 1)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 1 GiB device copy (HBM ceiling; counter calibration)")
     args = ap.parse_args()
@@ -368,6 +409,11 @@ def main():
     }
     sim.close()
     del sim
+    if not args.no_r1:
+        log("[bench] gradient-form collision on the same workload ...")
+        rec["r1"] = bench_r1(torch, capi, w, launch, args.r1_steps, 20)
+        rec["r1"]["ratio_to_plain"] = round(rec["r1"]["value"] / rec["value"], 4)
+        log(f"[bench] r1 {rec['r1']}")
     if not args.no_batch:
         log("[bench] batched workload ...")
         rec["batched"] = bench_batch(torch, capi, W, args.batch_steps, 10, args.seed)

@@ -72,11 +72,19 @@ typedef struct {
     int volume_correction;   /* 1: apply the correction of Eq. (53) every step */
     int wall_compression;    /* compressive flux phi(1-phi)n on wall nodes: 0 -> zero,
                                 1 -> g (1 - g) times the unit corrected gradient of Eq. (45) */
+    int collision;           /* non-equilibrium moment A2 of the regularised populations, Eq. (14):
+                                0 -> the local second moment of the pre-collision populations;
+                                1 -> the gradient form of Eq. (15), -(c_s^2/omega)(grad u + grad u^T),
+                                     from the isotropic stencil of Eq. (22) with u = 0 on solid nodes
+                                     (the thread-safe formulation of Sec. II A: no populations are
+                                     stored between steps).  With 1, cac_get_populations, the
+                                     adjoint (cac_tape_*, cac_adjoint) and batches are refused
+                                     with CAC_ERR_STATE / CAC_ERR_ARG. */
 } cac_params;
 
 /* Fill p with the defaults (rho = 1, nu = 0.04, sigma = 0.02, delta = 4,
  * D = 0.1, g = 0, eps_phi = 1e-3, eps_n = 1e-12, sin_tol = 1e-6,
- * cot_max = 1e6, volume_correction = 1, wall_compression = 1). */
+ * cot_max = 1e6, volume_correction = 1, wall_compression = 1, collision = 0). */
 cac_status cac_default_params(cac_params *p);
 
 /* Create a handle for an nx * ny * nz lattice on the current HIP device.
@@ -144,7 +152,8 @@ cac_status cac_volume(cac_handle *h, double *out_host);
 cac_status cac_get_fields(cac_handle *h, float *d_phi, float *d_u, float *d_pstar);
 
 /* Copy out the post-collision populations of the last step (device, 27 N),
- * defined on fluid nodes. */
+ * defined on fluid nodes.  CAC_ERR_STATE with collision = 1 (no populations
+ * are stored). */
 cac_status cac_get_populations(cac_handle *h, float *d_f);
 
 /* Wait for the handle's stream and report the watchdog flag
@@ -188,7 +197,8 @@ cac_status cac_pull_copy_probe(cac_handle *h, int reps, double *ms);
 
 /* Size in bytes of a saved state (cac_save_state): a 64-byte header plus
  * 33 N floats (populations, phi with the current and the previous ghosts,
- * velocity, initial p*). */
+ * velocity, initial p*).  With collision = 1 the population planes hold the
+ * record of the last collision (p*, a, omega) instead. */
 cac_status cac_state_bytes(cac_handle *h, size_t *bytes);
 
 /* Checkpoint: copy the complete state (populations, phi and ghosts, velocity,
@@ -200,8 +210,8 @@ cac_status cac_save_state(cac_handle *h, void *d_buf, size_t bytes);
 /* Resume from a buffer written by cac_save_state on a handle with the same
  * lattice size; the geometry and angles are those set on this handle.  Stepping
  * after a load reproduces the saved run bit for bit.  Discards an adjoint
- * recording.  Errors: CAC_ERR_ARG (size or header mismatch), CAC_ERR_STATE (no
- * geometry). */
+ * recording.  Errors: CAC_ERR_ARG (size or header mismatch, or a state saved
+ * with another collision setting), CAC_ERR_STATE (no geometry). */
 cac_status cac_load_state(cac_handle *h, const void *d_buf, size_t bytes);
 
 /* Test hook: run one substep of the next step, in order 0 = W ghost update

@@ -779,7 +779,7 @@ int orc_step(const orc_params *p, int nx, int ny, int nz, const uint8_t *solid, 
     const long N = (long)nx * ny * nz;
     double *phi_hat = malloc(sizeof(double) * N);
     double *phistar = malloc(sizeof(double) * N);
-    double *f_new = malloc(sizeof(double) * Q * N);
+    double *f_new = calloc((size_t)Q * N, sizeof(double));
     double *a_wall = malloc(sizeof(double) * 3 * N);
     if (!phi_hat || !phistar || !f_new || !a_wall) return -1;
     int rc = 0;

@@ -355,7 +355,8 @@ cac_status cac_batch_init(cac_batch **bp, int ndom, const cac_domain_desc *d, ca
     *bp = nullptr;
     unsigned long long Ntot = 0;
     for (int k = 0; k < ndom; ++k) {
-        if (d[k].nx < 2 || d[k].ny < 2 || d[k].nz < 2 || !d[k].solid || !d[k].d_phi0 || !valid_params(d[k].params))
+        if (d[k].nx < 2 || d[k].ny < 2 || d[k].nz < 2 || !d[k].solid || !d[k].d_phi0 || !valid_params(d[k].params) ||
+            d[k].params.collision != 0)
             return CAC_ERR_ARG;
         Ntot += (unsigned long long)d[k].nx * d[k].ny * d[k].nz;
     }
@@ -579,7 +580,7 @@ cac_status cac_batch_get_fields(cac_batch *b, int k, float *d_phi, float *d_u, f
     if (!b || k < 0 || k >= b->ndom) return CAC_ERR_ARG;
     const Fields F = domain_fields(b, k);
     const Grid &g = b->dom[k].g;
-    if (d_phi || d_pstar) BCHK(b, launch_gather(g, F, b->cur, b->cur, b->steps > 0, d_phi, d_pstar, b->stream));
+    if (d_phi || d_pstar) BCHK(b, launch_gather(g, F, b->cur, b->cur, b->steps > 0, 27, d_phi, d_pstar, b->stream));
     if (d_u) BCHK(b, hipMemcpyAsync(d_u, F.u, 3 * (size_t)g.N * sizeof(float), hipMemcpyDeviceToDevice, b->stream));
     return CAC_OK;
 }

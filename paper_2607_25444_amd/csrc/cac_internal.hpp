@@ -149,6 +149,14 @@ PhaseTiling phase_tiling(const Grid &g, int bx, int by);
 hipError_t launch_ghost(const Grid &g, const DevParams &p, const Fields &F, int cur, hipStream_t s);
 hipError_t launch_hydro(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, int fcur, int pcur,
                         hipStream_t s);
+// Gradient-form hydrodynamic substep (collision = 1): coefficients of the
+// post-collision populations from the record in F.f[1] and the velocity
+// field into F.f[0]; then pull, moments and collision into the record and u
+// (self = the first step after the state is set: each node pulls its own
+// equilibrium).
+hipError_t launch_r1_coef(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, hipStream_t s);
+hipError_t launch_r1_stream(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, int pcur, bool self,
+                            hipStream_t s);
 hipError_t launch_phase(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, int pcur,
                         hipStream_t s);
 uint32_t phase_tiles(const Grid &g, const Tiling &t);  // workgroups (and FP64 partials) of the phase kernel
@@ -160,7 +168,10 @@ hipError_t launch_init(const Grid &g, const Fields &F, int fcur, const float *u0
                        hipStream_t s);
 hipError_t launch_mass(const Grid &g, const Tiling &t, const Fields &F, const float *phi, double *out,
                        hipStream_t s);
-hipError_t launch_gather(const Grid &g, const Fields &F, int fcur, int pcur, int stepped, float *phi_out,
+// p* on fluid nodes after a step: the sum of the first `npl` planes of
+// F.f[fcur] (27: the post-collision populations; 1: the record of the
+// gradient-form path).
+hipError_t launch_gather(const Grid &g, const Fields &F, int fcur, int pcur, int stepped, int npl, float *phi_out,
                          float *pstar_out, hipStream_t s);
 
 // ---------------------------------------------------------------- adjoint

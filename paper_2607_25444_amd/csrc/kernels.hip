@@ -213,11 +213,12 @@ __global__ __launch_bounds__(1024) void k_mass_final(const double2 *__restrict__
 
 // Fields for output: phi from the current buffer on fluid nodes and from the
 // buffer holding the latest ghosts on solid nodes; p* as the zeroth moment of
-// the post-collision populations (equal to p* of the last collision).
+// the post-collision populations (equal to p* of the last collision), or, on
+// the gradient-form path, the p* plane of the record (npl = 1).
 __global__ __launch_bounds__(256) void k_gather(uint32_t N, const uint8_t *__restrict__ solid,
                                                 const float *__restrict__ phi_fluid,
                                                 const float *__restrict__ phi_ghost, const float *__restrict__ f,
-                                                const float *__restrict__ pstar0, int stepped,
+                                                const float *__restrict__ pstar0, int stepped, int npl,
                                                 float *__restrict__ phi_out, float *__restrict__ ps_out)
 {
     const uint32_t n = blockIdx.x * 256u + threadIdx.x;
@@ -229,8 +230,7 @@ __global__ __launch_bounds__(256) void k_gather(uint32_t N, const uint8_t *__res
         if (!stepped) {
             v = pstar0[n];
         } else if (!sol) {
-#pragma unroll
-            for (int i = 0; i < 27; ++i) v += f[(uint32_t)i * N + n];
+            for (int i = 0; i < npl; ++i) v += f[(uint32_t)i * N + n];
         }
         ps_out[n] = v;
     }
@@ -406,11 +406,11 @@ hipError_t launch_mass(const Grid &g, const Tiling &t, const Fields &F, const fl
     return hipGetLastError();
 }
 
-hipError_t launch_gather(const Grid &g, const Fields &F, int fcur, int pcur, int stepped, float *phi_out,
+hipError_t launch_gather(const Grid &g, const Fields &F, int fcur, int pcur, int stepped, int npl, float *phi_out,
                          float *pstar_out, hipStream_t s)
 {
     k_gather<<<blocks_for(g.N, 256), 256, 0, s>>>(g.N, F.solid, F.phi[pcur], F.phi[pcur ^ 1], F.f[fcur], F.pstar0,
-                                                  stepped, phi_out, pstar_out);
+                                                  stepped, npl, phi_out, pstar_out);
     return hipGetLastError();
 }
 

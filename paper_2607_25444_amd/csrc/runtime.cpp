@@ -57,7 +57,7 @@ namespace cac {
 bool valid_params(const cac_params &p)
 {
     return p.rho_l > 0 && p.rho_g > 0 && p.nu_l > 0 && p.nu_g > 0 && p.delta > 0 && p.D >= 0 && p.sigma >= 0 &&
-           p.eps_phi >= 0 && p.eps_phi < 0.5;
+           p.eps_phi >= 0 && p.eps_phi < 0.5 && (p.collision == 0 || p.collision == 1);
 }
 
 DevParams make_dev_params(const cac_params &p)
@@ -181,11 +181,22 @@ void build_geometry(const Grid &g, const uint8_t *solid, std::vector<uint32_t> &
 
 namespace cac {
 
+hipError_t launch_h(cac_handle *h, int c)
+{
+    if (h->prm.collision == 0) return launch_hydro(h->g, h->t, h->dp, h->F, c, c, h->stream);
+    // gradient form: the first step after the state is set pulls each node's own equilibrium
+    if (h->steps > 0) {
+        const hipError_t e = launch_r1_coef(h->g, h->t, h->dp, h->F, h->stream);
+        if (e != hipSuccess) return e;
+    }
+    return launch_r1_stream(h->g, h->t, h->dp, h->F, c, h->steps == 0, h->stream);
+}
+
 cac_status run_step(cac_handle *h)
 {
     const int c = h->cur;
     HIPCHK(h, launch_ghost(h->g, h->dp, h->F, c, h->stream));
-    HIPCHK(h, launch_hydro(h->g, h->t, h->dp, h->F, c, c, h->stream));
+    HIPCHK(h, launch_h(h, c));
     HIPCHK(h, launch_phase(h->g, h->t, h->dp, h->F, c, h->stream));
     HIPCHK(h, launch_volume(h->g, h->t, h->dp, h->F, c ^ 1, h->stream));
     h->cur ^= 1;
@@ -275,6 +286,7 @@ cac_status cac_default_params(cac_params *p)
     p->cot_max = 1e6;
     p->volume_correction = 1;
     p->wall_compression = 1;
+    p->collision = 0;
     return CAC_OK;
 }
 
@@ -465,7 +477,8 @@ cac_status cac_set_state(cac_handle *h, const float *d_phi, const float *d_u, co
         HIPCHK(h, hipMemsetAsync(F.pstar0, 0, N * sizeof(float), h->stream));
     HIPCHK(h, hipMemsetAsync(F.a, 0, 3 * N * sizeof(float), h->stream));
     HIPCHK(h, hipMemsetAsync(F.flag, 0, 256, h->stream));
-    HIPCHK(h, launch_init(h->g, F, 0, d_u, d_pstar, h->stream));
+    // the gradient-form path stores no populations: its first step reads p*0 and u0
+    if (h->prm.collision == 0) HIPCHK(h, launch_init(h->g, F, 0, d_u, d_pstar, h->stream));
     HIPCHK(h, launch_mass(h->g, h->t, F, F.phi[0], F.scal + 0, h->stream));
     if (h->debug & CAC_DEBUG_POISON) HIPCHK(h, launch_poison(h->g, F, h->stream));
     h->cur = 0;
@@ -483,7 +496,8 @@ cac_status cac_step(cac_handle *h, int nsteps)
     if (!h->state) return fail(h, CAC_ERR_STATE, "cac_set_state must come first");
     if (h->sub != 0) return fail(h, CAC_ERR_STATE, "a step was started with cac_debug_substep");
     for (int k = 0; k < nsteps; ++k) {
-        if (h->use_graph) {
+        // the first gradient-form step differs from the others: launched directly
+        if (h->use_graph && !(h->prm.collision == 1 && h->steps == 0)) {
             const int par = h->cur;
             if (!h->gexec[par]) {
                 cac_status st = capture_step(h, par);
@@ -523,8 +537,11 @@ cac_status cac_get_fields(cac_handle *h, float *d_phi, float *d_u, float *d_psta
 {
     if (!h) return CAC_ERR_ARG;
     if (!h->state) return fail(h, CAC_ERR_STATE, "no state");
-    if (d_phi || d_pstar)
-        HIPCHK(h, launch_gather(h->g, h->F, h->cur, h->cur, h->steps > 0, d_phi, d_pstar, h->stream));
+    if (d_phi || d_pstar) {
+        const bool r1 = h->prm.collision == 1;
+        HIPCHK(h, launch_gather(h->g, h->F, r1 ? 1 : h->cur, h->cur, h->steps > 0, r1 ? 1 : 27, d_phi, d_pstar,
+                                h->stream));
+    }
     if (d_u)
         HIPCHK(h, hipMemcpyAsync(d_u, h->F.u, 3 * (size_t)h->g.N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
     return CAC_OK;
@@ -534,6 +551,7 @@ cac_status cac_get_populations(cac_handle *h, float *d_f)
 {
     if (!h || !d_f) return CAC_ERR_ARG;
     if (!h->state) return fail(h, CAC_ERR_STATE, "no state");
+    if (h->prm.collision != 0) return fail(h, CAC_ERR_STATE, "the gradient-form collision stores no populations");
     HIPCHK(h, hipMemcpyAsync(d_f, h->F.f[h->cur], 27 * (size_t)h->g.N * sizeof(float), hipMemcpyDeviceToDevice,
                              h->stream));
     return CAC_OK;
@@ -606,7 +624,7 @@ cac_status cac_profile_step(cac_handle *h, int nsteps, double *ms)
         HIPCHK(h, hipEventRecord(e[0], h->stream));
         HIPCHK(h, launch_ghost(h->g, h->dp, h->F, c, h->stream));
         HIPCHK(h, hipEventRecord(e[1], h->stream));
-        HIPCHK(h, launch_hydro(h->g, h->t, h->dp, h->F, c, c, h->stream));
+        HIPCHK(h, launch_h(h, c));
         HIPCHK(h, hipEventRecord(e[2], h->stream));
         HIPCHK(h, launch_phase(h->g, h->t, h->dp, h->F, c, h->stream));
         HIPCHK(h, hipEventRecord(e[3], h->stream));
@@ -650,11 +668,15 @@ cac_status cac_save_state(cac_handle *h, void *d_buf, size_t bytes)
     const int c = h->cur;
     char *b = (char *)d_buf;
     uint64_t hdr[3] = {kStateMagic, (uint64_t)N, (uint64_t)h->steps};
+    const uint64_t coll = (uint64_t)h->prm.collision;
     HIPCHK(h, hipStreamSynchronize(h->stream));
     HIPCHK(h, hipMemcpy(b, hdr, sizeof hdr, hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(b + 32, &coll, sizeof coll, hipMemcpyHostToDevice));
     HIPCHK(h, hipMemcpyAsync(b + 24, h->F.scal, sizeof(double), hipMemcpyDeviceToDevice, h->stream));
     float *a = (float *)(b + kStateHeader);
-    HIPCHK(h, hipMemcpyAsync(a, h->F.f[c], 27 * N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    // the 27 population planes, or the record planes of the gradient-form path
+    const float *fsrc = h->prm.collision == 1 ? h->F.f[1] : h->F.f[c];
+    HIPCHK(h, hipMemcpyAsync(a, fsrc, 27 * N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(a + 27 * N, h->F.phi[c], N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(a + 28 * N, h->F.phi[c ^ 1], N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(a + 29 * N, h->F.u, 3 * N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
@@ -669,14 +691,19 @@ cac_status cac_load_state(cac_handle *h, const void *d_buf, size_t bytes)
     if (bytes < state_bytes(h)) return fail(h, CAC_ERR_ARG, "buffer of %zu bytes, %zu needed", bytes, state_bytes(h));
     const size_t N = h->g.N;
     const char *b = (const char *)d_buf;
-    uint64_t hdr[3];
+    uint64_t hdr[3], coll = 0;
     HIPCHK(h, hipStreamSynchronize(h->stream));
     HIPCHK(h, hipMemcpy(hdr, b, sizeof hdr, hipMemcpyDeviceToHost));
+    HIPCHK(h, hipMemcpy(&coll, b + 32, sizeof coll, hipMemcpyDeviceToHost));
     if (hdr[0] != kStateMagic || hdr[1] != (uint64_t)N)
         return fail(h, CAC_ERR_ARG, "not a saved state of a lattice of this size");
+    if (coll != (uint64_t)h->prm.collision)
+        return fail(h, CAC_ERR_ARG, "state saved with collision = %llu, handle has %d", (unsigned long long)coll,
+                    h->prm.collision);
     const float *a = (const float *)(b + kStateHeader);
     HIPCHK(h, hipMemcpyAsync(h->F.scal, b + 24, sizeof(double), hipMemcpyDeviceToDevice, h->stream));
-    HIPCHK(h, hipMemcpyAsync(h->F.f[0], a, 27 * N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->F.f[h->prm.collision == 1 ? 1 : 0], a, 27 * N * sizeof(float),
+                             hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->F.phi[0], a + 27 * N, N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->F.phi[1], a + 28 * N, N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->F.u, a + 29 * N, 3 * N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
@@ -702,7 +729,7 @@ cac_status cac_debug_substep(cac_handle *h, int which)
     const int c = h->cur;
     switch (which) {
     case 0: HIPCHK(h, launch_ghost(h->g, h->dp, h->F, c, h->stream)); break;
-    case 1: HIPCHK(h, launch_hydro(h->g, h->t, h->dp, h->F, c, c, h->stream)); break;
+    case 1: HIPCHK(h, launch_h(h, c)); break;
     case 2: HIPCHK(h, launch_phase(h->g, h->t, h->dp, h->F, c, h->stream)); break;
     case 3:
         HIPCHK(h, launch_volume(h->g, h->t, h->dp, h->F, c ^ 1, h->stream));

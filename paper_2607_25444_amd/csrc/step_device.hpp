@@ -283,6 +283,94 @@ __host__ __device__ __forceinline__ void pair_moments(const float (&f)[27], floa
 
 // ------------------------------------------------------------------ H: hydro
 
+// Macroscopic part of the collision at a fluid node (Sec. II A) from the
+// kinetic moments mom = (p*, j, P) of the pulled populations and the phi
+// stencil (value ph, gradient g, Laplacian lap): mu_phi and F_sigma
+// (Eq. (19)), mixture laws (Eqs. (8)-(10)), F_p (Eq. (20)), F_ext and F_nu
+// (Eq. (21), with the equilibrium at u' = j + a'/2 built without F_nu), the
+// acceleration a = F/rho and u = j + a/2 (Eq. (7)).
+struct Macro {
+    float ps, ux, uy, uz, ax, ay, az, omega;
+};
+
+__device__ __forceinline__ Macro macro_node(const DevParams &p, float ph, float gx, float gy, float gz, float lap,
+                                            const float (&mom)[10])
+{
+    const float ps = mom[0], jx = mom[1], jy = mom[2], jz = mom[3];
+    const float Pxx = mom[4], Pyy = mom[5], Pzz = mom[6], Pxy = mom[7], Pxz = mom[8], Pyz = mom[9];
+    const float mu_phi = p.beta4 * ph * (ph - 1.0f) * (ph - 0.5f) - p.kappa_phi * lap;
+    float Fx = mu_phi * gx, Fy = mu_phi * gy, Fz = mu_phi * gz;
+    const float rho = p.rho_g + p.drho * ph;
+    const float irho = fast_rcp(rho);
+    const float nu = (p.mu_g + p.dmu * ph) * irho;
+    const float omega = fast_rcp(0.5f + 3.0f * nu);
+    float ax, ay, az;
+    if (p.variable_density) {
+        const float grx = p.drho * gx, gry = p.drho * gy, grz = p.drho * gz;
+        const float cp = -ps * (1.0f / 3.0f);
+        const float fe = p.drho * ph;
+        Fx += cp * grx + fe * p.gx;
+        Fy += cp * gry + fe * p.gy;
+        Fz += cp * grz + fe * p.gz;
+        const float a1x = Fx * irho, a1y = Fy * irho, a1z = Fz * irho;
+        const float ux1 = jx + 0.5f * a1x, uy1 = jy + 0.5f * a1y, uz1 = jz + 0.5f * a1z;
+        const float p3 = ps * (1.0f / 3.0f);
+        const float Qxx = Pxx - p3 - ux1 * ux1, Qyy = Pyy - p3 - uy1 * uy1, Qzz = Pzz - p3 - uz1 * uz1;
+        const float Qxy = Pxy - ux1 * uy1, Qxz = Pxz - ux1 * uz1, Qyz = Pyz - uy1 * uz1;
+        const float cnu = -3.0f * nu * omega * irho;
+        ax = a1x + cnu * (Qxx * grx + Qxy * gry + Qxz * grz);
+        ay = a1y + cnu * (Qxy * grx + Qyy * gry + Qyz * grz);
+        az = a1z + cnu * (Qxz * grx + Qyz * gry + Qzz * grz);
+    } else {
+        ax = Fx * irho;
+        ay = Fy * irho;
+        az = Fz * irho;
+    }
+    Macro M;
+    M.ps = ps;
+    M.ux = jx + 0.5f * ax;
+    M.uy = jy + 0.5f * ay;
+    M.uz = jz + 0.5f * az;
+    M.ax = ax;
+    M.ay = ay;
+    M.az = az;
+    M.omega = omega;
+    return M;
+}
+
+// Hermite coefficients of the post-collision populations (Eqs. (3), (11),
+// (14), (16), (17) with the trapezoidal shift):
+//   f*_i = w_i [p* + 3 c.(u + a/2) + 4.5 H2:C2 + 4.5 H3:C3],
+//   C2 = uu + (ua + au)/2 + (1 - omega) A2,  C3 = uuu + (1 - omega) S(u A2),
+// A2 = (xx, yy, zz, xy, xz, yz) the non-equilibrium moment.
+__device__ __forceinline__ Herm herm_post(const Macro &M, const float (&A2)[6])
+{
+    const float ux = M.ux, uy = M.uy, uz = M.uz, ax = M.ax, ay = M.ay, az = M.az;
+    const float A2xx = A2[0], A2yy = A2[1], A2zz = A2[2], A2xy = A2[3], A2xz = A2[4], A2yz = A2[5];
+    const float om1 = 1.0f - M.omega;
+    Herm h;
+    h.ps = M.ps;
+    h.bx = ux + 0.5f * ax;
+    h.by = uy + 0.5f * ay;
+    h.bz = uz + 0.5f * az;
+    h.xx = ux * ux + ux * ax + om1 * A2xx;
+    h.yy = uy * uy + uy * ay + om1 * A2yy;
+    h.zz = uz * uz + uz * az + om1 * A2zz;
+    h.xy = ux * uy + 0.5f * (ux * ay + ax * uy) + om1 * A2xy;
+    h.xz = ux * uz + 0.5f * (ux * az + ax * uz) + om1 * A2xz;
+    h.yz = uy * uz + 0.5f * (uy * az + ay * uz) + om1 * A2yz;
+    h.tr3 = (h.xx + h.yy + h.zz) * (1.0f / 3.0f);
+    // C3 = uuu + (1 - omega)(u_a A2_bg + u_b A2_ag + u_g A2_ab)
+    h.xxy = ux * ux * uy + om1 * (2.0f * ux * A2xy + uy * A2xx);
+    h.xxz = ux * ux * uz + om1 * (2.0f * ux * A2xz + uz * A2xx);
+    h.yyx = uy * uy * ux + om1 * (2.0f * uy * A2xy + ux * A2yy);
+    h.yyz = uy * uy * uz + om1 * (2.0f * uy * A2yz + uz * A2yy);
+    h.zzx = uz * uz * ux + om1 * (2.0f * uz * A2xz + ux * A2zz);
+    h.zzy = uz * uz * uy + om1 * (2.0f * uz * A2yz + uy * A2zz);
+    h.xyz = ux * uy * uz + om1 * (ux * A2yz + uy * A2xz + uz * A2xy);
+    return h;
+}
+
 // Fused pull collide-stream at fluid node x (Sec. II A):
 //   pull f_i(x) = f*_i(x - c_i), or f*_opp(i)(x) when x - c_i is solid
 //   (halfway bounce-back); phi stencil -> grad, lap (Eqs. (22)-(23));
@@ -330,70 +418,22 @@ __device__ __forceinline__ void hydro_node(const Grid &g, const DevParams &p, co
     // kinetic moments
     float mom[10];
     pair_moments(f, mom);
-    const float ps = mom[0], jx = mom[1], jy = mom[2], jz = mom[3];
+    const float ps = mom[0];
     const float Pxx = mom[4], Pyy = mom[5], Pzz = mom[6], Pxy = mom[7], Pxz = mom[8], Pyz = mom[9];
 
-    // chemical potential, capillary force, mixture properties
-    const float mu_phi = p.beta4 * ph * (ph - 1.0f) * (ph - 0.5f) - p.kappa_phi * lap;
-    float Fx = mu_phi * gx, Fy = mu_phi * gy, Fz = mu_phi * gz;
-    const float rho = p.rho_g + p.drho * ph;
-    const float irho = fast_rcp(rho);
-    const float nu = (p.mu_g + p.dmu * ph) * irho;
-    const float omega = fast_rcp(0.5f + 3.0f * nu);
-    float ax, ay, az;
-    if (p.variable_density) {
-        const float grx = p.drho * gx, gry = p.drho * gy, grz = p.drho * gz;
-        const float cp = -ps * (1.0f / 3.0f);
-        const float fe = p.drho * ph;
-        Fx += cp * grx + fe * p.gx;
-        Fy += cp * gry + fe * p.gy;
-        Fz += cp * grz + fe * p.gz;
-        const float a1x = Fx * irho, a1y = Fy * irho, a1z = Fz * irho;
-        const float ux1 = jx + 0.5f * a1x, uy1 = jy + 0.5f * a1y, uz1 = jz + 0.5f * a1z;
-        const float p3 = ps * (1.0f / 3.0f);
-        const float Qxx = Pxx - p3 - ux1 * ux1, Qyy = Pyy - p3 - uy1 * uy1, Qzz = Pzz - p3 - uz1 * uz1;
-        const float Qxy = Pxy - ux1 * uy1, Qxz = Pxz - ux1 * uz1, Qyz = Pyz - uy1 * uz1;
-        const float cnu = -3.0f * nu * omega * irho;
-        ax = a1x + cnu * (Qxx * grx + Qxy * gry + Qxz * grz);
-        ay = a1y + cnu * (Qxy * grx + Qyy * gry + Qyz * grz);
-        az = a1z + cnu * (Qxz * grx + Qyz * gry + Qzz * grz);
-    } else {
-        ax = Fx * irho;
-        ay = Fy * irho;
-        az = Fz * irho;
-    }
-    const float ux = jx + 0.5f * ax, uy = jy + 0.5f * ay, uz = jz + 0.5f * az;
+    const Macro M = macro_node(p, ph, gx, gy, gz, lap, mom);
+    const float ux = M.ux, uy = M.uy, uz = M.uz, ax = M.ax, ay = M.ay, az = M.az;
 
     // A2 (R2 reading: local second moment of f - f^eq + S/2)
     const float p3 = ps * (1.0f / 3.0f);
-    const float A2xx = Pxx - p3 - ux * ux + ux * ax;
-    const float A2yy = Pyy - p3 - uy * uy + uy * ay;
-    const float A2zz = Pzz - p3 - uz * uz + uz * az;
-    const float A2xy = Pxy - ux * uy + 0.5f * (ux * ay + ax * uy);
-    const float A2xz = Pxz - ux * uz + 0.5f * (ux * az + ax * uz);
-    const float A2yz = Pyz - uy * uz + 0.5f * (uy * az + ay * uz);
-    const float om1 = 1.0f - omega;
-
-    Herm h;
-    h.ps = ps;
-    h.bx = ux + 0.5f * ax;
-    h.by = uy + 0.5f * ay;
-    h.bz = uz + 0.5f * az;
-    h.xx = ux * ux + ux * ax + om1 * A2xx;
-    h.yy = uy * uy + uy * ay + om1 * A2yy;
-    h.zz = uz * uz + uz * az + om1 * A2zz;
-    h.xy = ux * uy + 0.5f * (ux * ay + ax * uy) + om1 * A2xy;
-    h.xz = ux * uz + 0.5f * (ux * az + ax * uz) + om1 * A2xz;
-    h.yz = uy * uz + 0.5f * (uy * az + ay * uz) + om1 * A2yz;
-    h.tr3 = (h.xx + h.yy + h.zz) * (1.0f / 3.0f);
-    // C3 = uuu + (1 - omega)(u_a A2_bg + u_b A2_ag + u_g A2_ab)
-    h.xxy = ux * ux * uy + om1 * (2.0f * ux * A2xy + uy * A2xx);
-    h.xxz = ux * ux * uz + om1 * (2.0f * ux * A2xz + uz * A2xx);
-    h.yyx = uy * uy * ux + om1 * (2.0f * uy * A2xy + ux * A2yy);
-    h.yyz = uy * uy * uz + om1 * (2.0f * uy * A2yz + uz * A2yy);
-    h.zzx = uz * uz * ux + om1 * (2.0f * uz * A2xz + ux * A2zz);
-    h.zzy = uz * uz * uy + om1 * (2.0f * uz * A2yz + uy * A2zz);
-    h.xyz = ux * uy * uz + om1 * (ux * A2yz + uy * A2xz + uz * A2xy);
+    float A2[6];
+    A2[0] = Pxx - p3 - ux * ux + ux * ax;
+    A2[1] = Pyy - p3 - uy * uy + uy * ay;
+    A2[2] = Pzz - p3 - uz * uz + uz * az;
+    A2[3] = Pxy - ux * uy + 0.5f * (ux * ay + ax * uy);
+    A2[4] = Pxz - ux * uz + 0.5f * (ux * az + ax * uz);
+    A2[5] = Pyz - uy * uz + 0.5f * (uy * az + ay * uz);
+    const Herm h = herm_post(M, A2);
 
     const uint32_t n4 = 4u * n, N4 = 4u * N;
     __builtin_nontemporal_store(Lat::w(0) * (h.ps - 4.5f * h.tr3), &fout[n]);

@@ -1,0 +1,251 @@
+"""The gradient-form collision (collision = 1) on the GPU against the oracle.
+
+The library stores no populations on this path: a node keeps the record of
+its last collision (p*, u, a, omega); each step rebuilds the post-collision
+populations of every node from that record and the gradient-form moment of
+Eq. (15), and pulls them.  Checked here:
+* parity with the FP64 oracle (same switch): after one and a few steps every
+  fluid node of phi, u and p* and every ghost within 2e-6 (phi) and 1e-5 of the
+  maximum (u, p*); after 200 steps of the 32^3 sessile droplet phi within 1e-5
+  and u within 1e-4 of max |u| (the plain step's bar); the same on ragged tiles,
+  at density ratio 1000 with an initial velocity field, and at the full
+  256 x 256 x 128 size in the benchmark's launch;
+* bitwise: repeated runs, graph replay against eager launches, save / load /
+  resume, NaN poisoning of never-read data and reverse workgroup order;
+* refusals: population export, adjoint, batches.
+"""
+import numpy as np
+import pytest
+
+from paper_2607_25444_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(w, **kw):
+    p = dict(w.params)
+    p["collision"] = 1
+    p.update(kw)
+    return p
+
+
+def _sim(w, launch=None, **kw):
+    from paper_2607_25444_amd import capi
+    s = capi.Sim(w.shape, _params(w, **kw))
+    if launch:
+        s.set_launch(*launch)
+    s.set_geometry(w.solid, w.theta)
+    s.set_state(w.phi0, w.meta.get("u0"))
+    return s
+
+
+def gpu_run(w, steps, launch=None, **kw):
+    s = _sim(w, launch, **kw)
+    s.step(steps)
+    phi, u, ps = s.fields()
+    s.sync()
+    out = dict(phi=phi.cpu().numpy().astype(np.float64), u=u.cpu().numpy().astype(np.float64),
+               pstar=ps.cpu().numpy().astype(np.float64), volume=s.volume())
+    s.close()
+    return out
+
+
+def oracle_run(orc, w, steps, **kw):
+    u0 = w.meta.get("u0")
+    s = orc.OracleSim.create(w.shape, w.solid, w.theta.astype(np.float64), orc.Params(**_params(w, **kw)),
+                             w.phi0.astype(np.float64), u0=None if u0 is None else u0.astype(np.float64))
+    if steps:
+        s.step(steps)
+    return dict(phi=s.phi, u=s.u, pstar=s.pstar, M=s.M_target)
+
+
+def _cmp(g, o, w, orc, phi_tol, rel_tol):
+    fl = w.solid == 0
+    idx, _, _ = orc.wall_nodes(w.solid, w.shape)
+    N = w.N
+    dphi = np.abs(g["phi"] - o["phi"])
+    uo, ug = o["u"].reshape(3, N)[:, fl], g["u"].reshape(3, N)[:, fl]
+    po, pg = o["pstar"][fl], g["pstar"][fl]
+    e_u = np.abs(ug - uo).max() / max(np.abs(uo).max(), 1e-12)
+    e_p = np.abs(pg - po).max() / max(np.abs(po).max(), np.abs(uo).max(), 1e-4)
+    print(f"[r1] {w.name}: phi {dphi[fl].max():.2e} ghosts {dphi[idx].max() if len(idx) else 0:.2e} "
+          f"u {e_u:.2e} p* {e_p:.2e} (max|u| {np.abs(uo).max():.2e})", flush=True)
+    assert dphi[fl].max() <= phi_tol
+    if len(idx):
+        assert dphi[idx].max() <= phi_tol
+    assert e_u <= rel_tol
+    # p* is the zeroth moment of populations of size ~ max(|p*|, |u|), so its FP32
+    # rounding scales with that size
+    assert e_p <= rel_tol
+
+
+def _variable_density_case(shape=(20, 12, 14), seed=3):
+    """Random solids, density and viscosity contrast, gravity.  The droplet is
+    placed off the lattice's symmetry points: centred on a node, the point
+    midway between the droplet and its periodic image is a node where grad phi
+    vanishes in exact arithmetic, so the interface normal there (Eq. (25)) is
+    set by rounding alone once the field has moved.  That changes the FP64
+    phase update by up to 1e-5 when its inputs are rounded to FP32, for any
+    implementation; off-centre, the same test moves it by 2e-8."""
+    solid = W.random_geometry(shape, seed, n_blocks=3)
+    nx, ny, nz = shape
+    phi0 = W.tanh_droplet(shape, (nx / 2 + 0.37, ny / 2 - 0.29, nz / 2 + 0.21), 4.5, 4.0).astype(np.float32)
+    rng = np.random.default_rng(seed)
+    theta = np.deg2rad(rng.uniform(30, 150, size=nx * ny * nz)).astype(np.float32)
+    prm = W.default_params(rho_l=1.2, rho_g=0.9, nu_l=0.031, nu_g=0.24, sigma=0.025, g=(1e-5, -2e-5, -1e-4))
+    return W.Workload("vardens", shape, solid, theta, phi0, prm, 0)
+
+
+@pytest.mark.parametrize("steps", [1, 2, 5])
+@pytest.mark.parametrize("wc", [0, 1])
+def test_r1_initial_steps_all_fields(orc, steps, wc):
+    """Random voxel solids, per-node angles, density and viscosity contrast and a
+    body force.  Step 1 pulls each node's own equilibrium; from step 2 on the
+    populations come from the neighbours' records and velocity gradients."""
+    w = _variable_density_case()
+    _cmp(gpu_run(w, steps, wall_compression=wc), oracle_run(orc, w, steps, wall_compression=wc), w, orc, 2e-6, 1e-5)
+
+
+def test_r1_sessile_200_steps(orc):
+    """32^3 sessile droplet, theta = 60 deg, 200 steps: phi within 1e-5, u within
+    1e-4 of max |u|, the volume kept."""
+    w = W.sessile_32(60.0)
+    g, o = gpu_run(w, 200), oracle_run(orc, w, 200)
+    _cmp(g, o, w, orc, 1e-5, 1e-4)
+    assert g["volume"] == pytest.approx(o["M"], rel=1e-6)
+
+
+@pytest.mark.parametrize("launch", [(16, 4, 4, 0, 5), (32, 2, 4, 1, 3), (64, 2, 2, 0, 1), (128, 2, 1, 0, 6),
+                                    (512, 1, 1, 1, 3)])
+def test_r1_ragged_tiles(orc, launch):
+    """A grid that fills no tile exactly (70 x 37 x 19), random solids, 20 steps."""
+    shape = (70, 37, 19)
+    solid = W.random_geometry(shape, 11, n_blocks=6)
+    phi0 = W.tanh_droplet(shape, (30.2, 17.7, 7.1), 6.0, 4.0).astype(np.float32)
+    w = W.Workload("ragged", shape, solid, W.uniform_theta(shape, 75.0), phi0, W.default_params(), 0)
+    _cmp(gpu_run(w, 20, launch=launch), oracle_run(orc, w, 20), w, orc, 5e-6, 5e-5)
+
+
+def test_r1_impact_density_ratio_1000(orc):
+    """Droplet impact at density ratio 1000 from its initial velocity field,
+    100 steps: the plain step's bar."""
+    w = W.impact((40, 40, 36), R=9.0, We=10.0)
+    _cmp(gpu_run(w, 100), oracle_run(orc, w, 100), w, orc, 1e-5, 1e-4)
+
+
+def test_r1_full_size_spreading(orc):
+    """Spreading workload at full size (256 x 256 x 128) in the benchmark's launch,
+    three steps (the first pulls the equilibrium, the others the rebuilt
+    populations): every fluid node and ghost against the oracle."""
+    from paper_2607_25444_amd import tuning
+    w = W.spreading_256(0)
+    print(f"[r1] full size {w.name} N={w.N}", flush=True)
+    _cmp(gpu_run(w, 3, launch=tuning.launch_for(w.shape)), oracle_run(orc, w, 3), w, orc, 2e-6, 1e-5)
+
+
+def test_r1_uniform_flow_stays_uniform():
+    """Uniform velocity and phase field, no walls: the rebuilt populations are the
+    equilibrium and nothing changes beyond FP32 rounding."""
+    from paper_2607_25444_amd import capi
+    shape = (24, 20, 16)
+    N = 24 * 20 * 16
+    u0 = np.zeros((3, N), np.float32)
+    u0[0], u0[1], u0[2] = 0.02, -0.01, 0.015
+    s = capi.Sim(shape, W.default_params(rho_l=5.0, nu_l=0.02, nu_g=0.1, collision=1))
+    s.set_geometry(np.zeros(N, np.uint8), W.uniform_theta(shape, 90.0))
+    s.set_state(np.full(N, 0.3, np.float32), u0.reshape(-1))
+    s.step(20)
+    phi, u, _ = s.fields()
+    s.sync()
+    assert np.abs(u.cpu().numpy().reshape(3, N) - u0).max() < 1e-7
+    assert np.abs(phi.cpu().numpy() - 0.3).max() < 1e-7
+    s.close()
+
+
+def test_r1_deterministic_graph_and_resume():
+    """Two runs are bitwise equal; graph replay equals eager launches; a state
+    saved after 7 steps and loaded into a new handle continues bit for bit."""
+    from paper_2607_25444_amd import capi
+    w = W.sessile((40, 36, 20), 7.0, 110.0)
+    a = gpu_run(w, 15, launch=(16, 4, 4, 0))
+    b = gpu_run(w, 15, launch=(16, 4, 4, 0))
+    c = gpu_run(w, 15, launch=(16, 4, 4, 1))
+    for k in ("phi", "u", "pstar"):
+        np.testing.assert_array_equal(a[k], b[k])
+        np.testing.assert_array_equal(a[k], c[k])
+    s = _sim(w, (16, 4, 4, 1))
+    s.step(7)
+    buf = s.save_state()
+    s.step(8)
+    ref = [t.cpu().numpy() for t in s.fields()]
+    t = _sim(w, (16, 4, 4, 1))
+    t.load_state(buf)
+    t.step(8)
+    got = [x.cpu().numpy() for x in t.fields()]
+    for x, y in zip(ref, got):
+        np.testing.assert_array_equal(x, y)
+    np.testing.assert_array_equal(ref[0], a["phi"].astype(np.float32))
+    # a state of the local-moment collision is refused
+    r2 = capi.Sim(w.shape, w.params)
+    r2.set_geometry(w.solid, w.theta)
+    r2.set_state(w.phi0)
+    with pytest.raises(capi.CacError) as e:
+        t.load_state(r2.save_state())
+    assert e.value.status == capi.CAC_ERR_ARG
+    for x in (s, t, r2):
+        x.close()
+
+
+def _debug_case(seed=5):
+    shape = (48, 40, 36)
+    nx, ny, nz = shape
+    s = W.random_geometry(shape, seed, n_blocks=5).reshape(nz, ny, nx).copy()
+    s[:3] = 1
+    s[-3:] = 1
+    s[10:16, 8:14, 20:28] = 1
+    phi0 = W.tanh_droplet(shape, (20.3, 18.6, 9.2), 7.0, 4.0).astype(np.float32)
+    theta = np.deg2rad(np.random.default_rng(seed).uniform(40.0, 140.0, s.size)).astype(np.float32)
+    prm = W.default_params(rho_l=3.0, nu_l=0.05, nu_g=0.03, g=(0.0, 1e-5, -2e-5), collision=1)
+    return W.Workload("debug", shape, s.reshape(-1), theta, phi0, prm, 0)
+
+
+def test_r1_poison_and_reverse_order():
+    """NaN in every value the step must not read (records, coefficients and
+    velocity on solid nodes, phi inside solids) and workgroups in reverse
+    order: the fluid results are bitwise those of a plain run."""
+    from paper_2607_25444_amd import capi
+    w = _debug_case()
+    fl = w.solid == 0
+    out = []
+    for poison, rev in ((False, False), (True, True)):
+        s = capi.Sim(w.shape, w.params)
+        s.set_launch(32, 4, 2, use_graph=True)
+        s.set_debug(poison=poison, reverse_order=rev)
+        s.set_geometry(w.solid, w.theta)
+        s.set_state(w.phi0)
+        s.step(30)
+        phi, u, ps = s.fields()
+        s.sync()
+        out.append((phi.cpu().numpy()[fl], u.cpu().numpy().reshape(3, -1)[:, fl], ps.cpu().numpy()[fl]))
+        s.close()
+    for x, y in zip(*out):
+        assert np.isfinite(y).all()
+        np.testing.assert_array_equal(x, y)
+
+
+def test_r1_refusals():
+    """No populations to export, no adjoint, no batches with collision = 1."""
+    from paper_2607_25444_amd import capi
+    w = W.sessile((24, 20, 16), 5.0, 60.0)
+    s = _sim(w)
+    s.step(2)
+    with pytest.raises(capi.CacError) as e:
+        s.populations()
+    assert e.value.status == capi.CAC_ERR_STATE
+    with pytest.raises(capi.CacError) as e:
+        s.tape_forward(4, 2)
+    assert e.value.status == capi.CAC_ERR_STATE
+    s.close()
+    w2 = W.Workload(w.name, w.shape, w.solid, w.theta, w.phi0, _params(w), 0)
+    with pytest.raises(capi.CacError):
+        capi.Batch([w2])
