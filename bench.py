@@ -156,11 +156,11 @@ def bench_batch(torch, capi, W, steps, warmup, seed, singles=True, tune_cache=No
     return out
 
 
-# Gradient-form hydrodynamic substep (two kernels): coefficient pass reads the
-# record (p*, a, omega: 20 B) and the velocity (12 B) and writes 17 Hermite
-# coefficients (68 B); the stream pass reads the coefficients (68 B) and phi
-# (4 B) and writes the record (20 B) and the velocity (12 B).
-R1_HYDRO_BYTES_PER_LU = (5 + 3 + 17) * 4 + (17 + 1 + 5 + 3) * 4
+# Gradient-form hydrodynamic substep (two kernels): the rebuild pass reads the
+# record (p*, a, omega: 20 B) and the velocity (12 B) and writes the 27
+# post-collision populations (108 B); the stream pass reads the populations
+# (108 B) and phi (4 B) and writes the record (20 B) and the velocity (12 B).
+R1_HYDRO_BYTES_PER_LU = (5 + 3 + 27) * 4 + (27 + 1 + 5 + 3) * 4
 
 
 def bench_r1(torch, capi, w, launch, steps, warmup):

@@ -2,39 +2,40 @@
 // moment (collision = 1): the thread-safe formulation of Sec. II A, in which
 // both parts of the populations are rebuilt from macroscopic quantities.
 //
-// No populations are stored between steps.  The state of a node is its
-// record (p*, u, a, omega) of the last collision.  A step takes two kernels:
+// No populations are kept from one step to the next.  The state of a node is
+// its record (p*, u, a, omega) of the last collision.  A step takes two
+// kernels:
 //   k_r1_coef    A2 = -(c_s^2/omega)(grad u + grad u^T) (Eq. (15)) from the
 //                isotropic stencil (Eq. (22)) of the stored velocity field
-//                (u = 0 on solid nodes), then the 17 Hermite coefficients of
-//                the node's post-collision populations (Eqs. (3), (11), (14),
-//                (16), (17));
-//   k_r1_stream  each pulled population f_i(x) = f*_i(x - c_i) rebuilt from
-//                the coefficients of x - c_i (halfway bounce-back: f*_opp(i)
+//                (u = 0 on solid nodes), then the node's post-collision
+//                populations (Eqs. (3), (11), (14), (16), (17)), written once;
+//   k_r1_stream  pull f_i(x) = f*_i(x - c_i) (halfway bounce-back: f*_opp(i)
 //                of x itself), the kinetic moments, forces and velocity of
 //                the collision at x (Eqs. (6)-(10), (18)-(21)); writes the
 //                new record.  On the first step after the state is set, the
 //                pulled populations are the node's own equilibrium
 //                f^eq(p*0, u0) (the initial condition of the local-moment
 //                path).
+// Rebuilding each population at the pulling node instead (from the 17
+// Hermite coefficients of its source, 68 bytes per node) needs 314 gathers
+// per node against 27 here; on gfx950 that substep took 1.49 ms against
+// 0.57 ms on 256 x 256 x 128.
 //
 // Layout (structure of arrays, node index n):
-//   coefficient planes K[k*N + n], k = 0..16: p*, b = u + a/2 (3),
-//     C2 (xx, yy, zz, xy, xz, yz), C3 (xxy, xxz, yyx, yyz, zzx, zzy, xyz);
-//   record planes R[k*N + n], k = 0..4: p*, a (3), omega; u in its own array.
+//   rebuilt populations P[i*N + n] (27 planes) in the first population buffer;
+//   record planes R[k*N + n], k = 0..4: p*, a (3), omega, in the second; u in
+//   its own array.
 #include "step_device.hpp"
 
 namespace cac {
 
 namespace {
 
-enum : uint32_t { KPS = 0, KBX, KBY, KBZ, KXX, KYY, KZZ, KXY, KXZ, KYZ, KXXY, KXXZ, KYYX, KYYZ, KZZX, KZZY, KXYZ };
-
-// Gradient form of the non-equilibrium moment at fluid node y and the
-// coefficients of its post-collision populations.
+// Gradient form of the non-equilibrium moment at fluid node y and its
+// post-collision populations (non-temporal stores: read once, by the pull).
 __device__ __forceinline__ void r1_coef_node(const Grid &g, const Node &nd, const float *__restrict__ rec,
                                              const float *__restrict__ u, const uint32_t *__restrict__ nbr,
-                                             float *__restrict__ K)
+                                             float *__restrict__ fout)
 {
     if (!nd.in) return;
     const Offs o = node_offsets(g, nd.x, nd.y, nd.z);
@@ -81,61 +82,23 @@ __device__ __forceinline__ void r1_coef_node(const Grid &g, const Node &nd, cons
     A2[5] = c * (yz_ + zy_);
     const Herm h = herm_post(M, A2);
 
-    K[KPS * N + n] = h.ps;
-    K[KBX * N + n] = h.bx;
-    K[KBY * N + n] = h.by;
-    K[KBZ * N + n] = h.bz;
-    K[KXX * N + n] = h.xx;
-    K[KYY * N + n] = h.yy;
-    K[KZZ * N + n] = h.zz;
-    K[KXY * N + n] = h.xy;
-    K[KXZ * N + n] = h.xz;
-    K[KYZ * N + n] = h.yz;
-    K[KXXY * N + n] = h.xxy;
-    K[KXXZ * N + n] = h.xxz;
-    K[KYYX * N + n] = h.yyx;
-    K[KYYZ * N + n] = h.yyz;
-    K[KZZX * N + n] = h.zzx;
-    K[KZZY * N + n] = h.zzy;
-    K[KXYZ * N + n] = h.xyz;
+    __builtin_nontemporal_store(Lat::w(0) * (h.ps - 4.5f * h.tr3), &fout[n]);
+    static_for<13>([&](auto P) {
+        constexpr int i = 2 * P + 1;
+        float E, O;
+        herm_pair<i>(h, E, O);
+        __builtin_nontemporal_store(E + O, &fout[(uint32_t)i * N + n]);
+        __builtin_nontemporal_store(E - O, &fout[(uint32_t)(i + 1) * N + n]);
+    });
 }
 
-// Post-collision population I of the node at index y from its coefficients:
-//   w [p* + 3 c.b + 4.5 ((c_a c_b - delta_ab/3) C2_ab) + 4.5 H3:C3],
-// loading only the coefficients that link I carries on D3Q27.
-template <int I>
-__device__ __forceinline__ float herm_pop(const float *__restrict__ K, uint32_t N, uint32_t y)
-{
-    constexpr int cx = Lat::cx[I], cy = Lat::cy[I], cz = Lat::cz[I];
-    constexpr float hx = (float)(cx * cx) - 1.0f / 3.0f, hy = (float)(cy * cy) - 1.0f / 3.0f,
-                    hz = (float)(cz * cz) - 1.0f / 3.0f;
-    float cb = 0.f;
-    if constexpr (cx != 0) cb += (float)cx * K[KBX * N + y];
-    if constexpr (cy != 0) cb += (float)cy * K[KBY * N + y];
-    if constexpr (cz != 0) cb += (float)cz * K[KBZ * N + y];
-    float e2 = hx * K[KXX * N + y] + hy * K[KYY * N + y] + hz * K[KZZ * N + y];
-    if constexpr (cx * cy != 0) e2 += (float)(2 * cx * cy) * K[KXY * N + y];
-    if constexpr (cx * cz != 0) e2 += (float)(2 * cx * cz) * K[KXZ * N + y];
-    if constexpr (cy * cz != 0) e2 += (float)(2 * cy * cz) * K[KYZ * N + y];
-    // H3:C3 = 3 [hx (cy C_xxy + cz C_xxz) + hy (cx C_yyx + cz C_yyz) + hz (cx C_zzx + cy C_zzy)] + 6 cx cy cz C_xyz
-    float t = 0.f;
-    if constexpr (cy != 0) t += hx * (float)cy * K[KXXY * N + y];
-    if constexpr (cz != 0) t += hx * (float)cz * K[KXXZ * N + y];
-    if constexpr (cx != 0) t += hy * (float)cx * K[KYYX * N + y];
-    if constexpr (cz != 0) t += hy * (float)cz * K[KYYZ * N + y];
-    if constexpr (cx != 0) t += hz * (float)cx * K[KZZX * N + y];
-    if constexpr (cy != 0) t += hz * (float)cy * K[KZZY * N + y];
-    float h3 = 3.0f * t;
-    if constexpr (cx * cy * cz != 0) h3 += (float)(6 * cx * cy * cz) * K[KXYZ * N + y];
-    return Lat::w(I) * (K[KPS * N + y] + 3.0f * cb + 4.5f * e2 + 4.5f * h3);
-}
-
-// Stream and collide at fluid node x: pulled populations from the
-// coefficients of the source nodes, then the macroscopic part of the
-// collision; writes the record and u.
-template <bool SELF>
+// Stream and collide at fluid node x: pull of the rebuilt populations, then
+// the macroscopic part of the collision; writes the record and u.  NTL:
+// non-temporal population loads (row-wide tiles, as in the local-moment
+// kernel).
+template <bool SELF, bool NTL>
 __device__ __forceinline__ void r1_stream_node(const Grid &g, const DevParams &p, const Node &nd,
-                                               const float *__restrict__ K, const float *__restrict__ phi,
+                                               const float *__restrict__ fin, const float *__restrict__ phi,
                                                const uint32_t *__restrict__ nbr, const float *__restrict__ pstar0,
                                                float *__restrict__ u, float *__restrict__ rec,
                                                uint32_t *__restrict__ flag)
@@ -160,16 +123,7 @@ __device__ __forceinline__ void r1_stream_node(const Grid &g, const DevParams &p
             f[i] = feq_one<i>(ps0, ux0, uy0, uz0);
         });
     } else {
-        f[0] = herm_pop<0>(K, N, n);
-        static_for<26>([&](auto J) {
-            constexpr int i = J + 1;
-            constexpr int io = Lat::opp(i);
-            // the source x - c_i = x + c_opp(i) is solid when bit opp(i) is set
-            if ((m >> io) & 1u)
-                f[i] = herm_pop<io>(K, N, n);
-            else
-                f[i] = herm_pop<i>(K, N, at<-Lat::cx[i], -Lat::cy[i], -Lat::cz[i]>(o));
-        });
+        pull_populations<NTL>(g, o, n, m, fin, f);
     }
 
     float gx, gy, gz, lap;
@@ -194,24 +148,27 @@ __device__ __forceinline__ void r1_stream_node(const Grid &g, const DevParams &p
 template <int NT>
 __global__ __launch_bounds__(NT) void k_r1_coef(Grid g, Tiling t, DevParams p, const float *__restrict__ rec,
                                                 const float *__restrict__ u, const uint32_t *__restrict__ nbr,
-                                                float *__restrict__ K)
+                                                float *__restrict__ fout)
 {
     const uint32_t b = p.rev_order ? gridDim.x - 1u - blockIdx.x : blockIdx.x;
-    r1_coef_node(g, tile_node(g, t, xcd_tile(b, t.ntiles)), rec, u, nbr, K);
+    r1_coef_node(g, tile_node(g, t, xcd_tile(b, t.ntiles)), rec, u, nbr, fout);
 }
 
-template <int NT, bool SELF>
-__global__ __launch_bounds__(NT) void k_r1_stream(Grid g, Tiling t, DevParams p, const float *__restrict__ K,
+// Workgroup order as in the local-moment kernel: the hardware's with
+// non-temporal loads, XCD-contiguous tiles otherwise.
+template <int NT, bool SELF, bool NTL>
+__global__ __launch_bounds__(NT) void k_r1_stream(Grid g, Tiling t, DevParams p, const float *__restrict__ fin,
                                                   const float *__restrict__ phi, const uint32_t *__restrict__ nbr,
                                                   const float *__restrict__ pstar0, float *__restrict__ u,
                                                   float *__restrict__ rec, uint32_t *__restrict__ flag)
 {
     const uint32_t b = p.rev_order ? gridDim.x - 1u - blockIdx.x : blockIdx.x;
-    r1_stream_node<SELF>(g, p, tile_node(g, t, xcd_tile(b, t.ntiles)), K, phi, nbr, pstar0, u, rec, flag);
+    const uint32_t tile = NTL ? b : xcd_tile(b, t.ntiles);
+    r1_stream_node<SELF, NTL>(g, p, tile_node(g, t, tile), fin, phi, nbr, pstar0, u, rec, flag);
 }
 
-// The coefficient planes live in the first population buffer, the record in
-// the second (the collision = 1 path stores no populations).
+// The rebuilt populations live in the first population buffer, the record in
+// the second.
 hipError_t launch_r1_coef(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, hipStream_t s)
 {
     switch (t.bx * t.by * t.bz) {
@@ -226,13 +183,17 @@ hipError_t launch_r1_coef(const Grid &g, const Tiling &t, const DevParams &p, co
 hipError_t launch_r1_stream(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, int pcur, bool self,
                             hipStream_t s)
 {
+    const bool ntl = t.bx >= g.nx;
 #define CAC_R1S(NT_)                                                                                              \
     if (self)                                                                                                     \
-        k_r1_stream<NT_, true><<<t.ntiles, NT_, 0, s>>>(g, t, p, F.f[0], F.phi[pcur], F.nbr, F.pstar0, F.u,       \
-                                                        F.f[1], F.flag);                                          \
+        k_r1_stream<NT_, true, false><<<t.ntiles, NT_, 0, s>>>(g, t, p, F.f[0], F.phi[pcur], F.nbr, F.pstar0,     \
+                                                               F.u, F.f[1], F.flag);                              \
+    else if (ntl)                                                                                                 \
+        k_r1_stream<NT_, false, true><<<t.ntiles, NT_, 0, s>>>(g, t, p, F.f[0], F.phi[pcur], F.nbr, F.pstar0,     \
+                                                               F.u, F.f[1], F.flag);                              \
     else                                                                                                          \
-        k_r1_stream<NT_, false><<<t.ntiles, NT_, 0, s>>>(g, t, p, F.f[0], F.phi[pcur], F.nbr, F.pstar0, F.u,      \
-                                                         F.f[1], F.flag);
+        k_r1_stream<NT_, false, false><<<t.ntiles, NT_, 0, s>>>(g, t, p, F.f[0], F.phi[pcur], F.nbr, F.pstar0,    \
+                                                                F.u, F.f[1], F.flag);
     switch (t.bx * t.by * t.bz) {
     case 128: CAC_R1S(128) break;
     case 256: CAC_R1S(256) break;
