@@ -7,7 +7,8 @@
 // kernels:
 //   k_r1_coef    A2 = -(c_s^2/omega)(grad u + grad u^T) (Eq. (15)) from the
 //                isotropic stencil (Eq. (22)) of the stored velocity field
-//                (u = 0 on solid nodes), then the node's post-collision
+//                (u = 0 on solid nodes; the planes staged through LDS in
+//                column tiles), then the node's post-collision
 //                populations (Eqs. (3), (11), (14), (16), (17)), written once;
 //   k_r1_stream  pull f_i(x) = f*_i(x - c_i) (halfway bounce-back: f*_opp(i)
 //                of x itself), the kinetic moments, forces and velocity of
@@ -31,32 +32,14 @@ namespace cac {
 
 namespace {
 
-// Gradient form of the non-equilibrium moment at fluid node y and its
-// post-collision populations (non-temporal stores: read once, by the pull).
-__device__ __forceinline__ void r1_coef_node(const Grid &g, const Node &nd, const float *__restrict__ rec,
-                                             const float *__restrict__ u, const uint32_t *__restrict__ nbr,
-                                             float *__restrict__ fout)
+// Gradient form of the non-equilibrium moment at fluid node n (solid-neighbour
+// mask m) from its velocity stencil s*[k], k = (dz+1)*9 + (dy+1)*3 + (dx+1),
+// already zero on solid neighbours; then its post-collision populations
+// (non-temporal stores: read once, by the pull).
+__device__ __forceinline__ void r1_rebuild(uint32_t N, uint32_t n, const float (&sx)[27], const float (&sy)[27],
+                                           const float (&sz)[27], const float *__restrict__ rec,
+                                           float *__restrict__ fout)
 {
-    if (!nd.in) return;
-    const Offs o = node_offsets(g, nd.x, nd.y, nd.z);
-    const uint32_t n = at<0, 0, 0>(o);
-    const uint32_t m = nbr[n];
-    if (m & 1u) return;
-    const uint32_t N = g.N;
-
-    // velocity stencil, zero on solid neighbours (the walls are at rest)
-    float sx[27], sy[27], sz[27];
-    static_for<27>([&](auto J) {
-        constexpr int kk = J;
-        constexpr int dx = kk % 3 - 1, dy = (kk / 3) % 3 - 1, dz = kk / 9 - 1;
-        constexpr int li = Lat::idx(dx, dy, dz);
-        const uint32_t q = at<dx, dy, dz>(o);
-        const float vx = u[q], vy = u[N + q], vz = u[2u * N + q];
-        const bool sol = ((m >> li) & 1u) != 0u;
-        sx[kk] = sol ? 0.f : vx;
-        sy[kk] = sol ? 0.f : vy;
-        sz[kk] = sol ? 0.f : vz;
-    });
     // d_b u_a by the isotropic gradient of each component
     float xx_, xy_, xz_, yx_, yy_, yz_, zx_, zy_, zz_, l_;
     stencil_grad_lap(sx, xx_, yx_, zx_, l_);  // d_x u_x, d_y u_x, d_z u_x
@@ -145,13 +128,72 @@ __device__ __forceinline__ void r1_stream_node(const Grid &g, const DevParams &p
 
 }  // namespace
 
-template <int NT>
-__global__ __launch_bounds__(NT) void k_r1_coef(Grid g, Tiling t, DevParams p, const float *__restrict__ rec,
-                                                const float *__restrict__ u, const uint32_t *__restrict__ nbr,
-                                                float *__restrict__ fout)
+// Rebuild pass over column tiles of CX x CY nodes marching through a z-chunk:
+// the velocity planes z-1, z, z+1 (with a one-node halo in x and y) sit in a
+// ring of three LDS slots, so each velocity value is loaded from memory about
+// (CX+2)(CY+2)/(CX CY) times per chunk instead of 27 times.  Every thread
+// takes part in the loads and both barriers of each plane; threads outside the
+// grid skip only the node update.
+template <int CX, int CY>
+__global__ __launch_bounds__(CX *CY) void k_r1_coef(Grid g, PhaseTiling pt, DevParams p, const float *__restrict__ rec,
+                                                    const float *__restrict__ u, const uint32_t *__restrict__ nbr,
+                                                    float *__restrict__ fout)
 {
+    constexpr int LX = CX + 2, LP = (CX + 2) * (CY + 2);
+    __shared__ float su[3][3][LP];  // [slot][component][position]
     const uint32_t b = p.rev_order ? gridDim.x - 1u - blockIdx.x : blockIdx.x;
-    r1_coef_node(g, tile_node(g, t, xcd_tile(b, t.ntiles)), rec, u, nbr, fout);
+    const uint32_t tile = xcd_tile(b, pt.ntiles);
+    const uint32_t txy = (uint32_t)pt.ntx * (uint32_t)pt.nty;
+    const uint32_t zci = tile / txy, rxy = tile - zci * txy;
+    const uint32_t tyi = rxy / (uint32_t)pt.ntx, txi = rxy - tyi * (uint32_t)pt.ntx;
+    const int x0 = (int)txi * CX, y0 = (int)tyi * CY;
+    const int z0 = (int)zci * pt.zc, z1 = min(z0 + pt.zc, g.nz);
+    const int tid = (int)threadIdx.x, lx = tid % CX, ly = tid / CX;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool inxy = x < g.nx && y < g.ny;
+    const uint32_t N = g.N;
+
+    auto load_plane = [&](int slot, int zg) {
+        const uint32_t zo = (uint32_t)wrapc(zg, g.nz) * g.nxny;
+        for (int q = tid; q < LP; q += CX * CY) {
+            const int qx = q % LX, qy = q / LX;
+            const uint32_t gi =
+                (uint32_t)wrapc(x0 - 1 + qx, g.nx) + (uint32_t)wrapc(y0 - 1 + qy, g.ny) * (uint32_t)g.nx + zo;
+            su[slot][0][q] = u[gi];
+            su[slot][1][q] = u[N + gi];
+            su[slot][2][q] = u[2u * N + gi];
+        }
+    };
+    load_plane(0, z0 - 1);
+    load_plane(1, z0);
+    for (int z = z0; z < z1; ++z) {
+        const int k = z - z0;  // slots: z-1 -> k % 3, z -> (k+1) % 3, z+1 -> (k+2) % 3
+        load_plane((k + 2) % 3, z + 1);
+        __syncthreads();
+        if (inxy) {
+            const uint32_t n = (uint32_t)x + (uint32_t)y * (uint32_t)g.nx + (uint32_t)z * g.nxny;
+            const uint32_t m = nbr[n];
+            if (!(m & 1u)) {
+                const int sl[3] = {k % 3, (k + 1) % 3, (k + 2) % 3};
+                float sx[27], sy[27], sz[27];
+                static_for<27>([&](auto J) {
+                    constexpr int kk = J;
+                    constexpr int dx = kk % 3 - 1, dy = (kk / 3) % 3 - 1, dz = kk / 9 - 1;
+                    constexpr int li = Lat::idx(dx, dy, dz);
+                    const int q = (lx + 1 + dx) + LX * (ly + 1 + dy);
+                    const int sv = sl[dz + 1];
+                    // zero on solid neighbours (the walls are at rest)
+                    const bool sol = ((m >> li) & 1u) != 0u;
+                    const float vx = su[sv][0][q], vy = su[sv][1][q], vz = su[sv][2][q];
+                    sx[kk] = sol ? 0.f : vx;
+                    sy[kk] = sol ? 0.f : vy;
+                    sz[kk] = sol ? 0.f : vz;
+                });
+                r1_rebuild(N, n, sx, sy, sz, rec, fout);
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // Workgroup order as in the local-moment kernel: the hardware's with
@@ -171,12 +213,9 @@ __global__ __launch_bounds__(NT) void k_r1_stream(Grid g, Tiling t, DevParams p,
 // the second.
 hipError_t launch_r1_coef(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, hipStream_t s)
 {
-    switch (t.bx * t.by * t.bz) {
-    case 128: k_r1_coef<128><<<t.ntiles, 128, 0, s>>>(g, t, p, F.f[1], F.u, F.nbr, F.f[0]); break;
-    case 256: k_r1_coef<256><<<t.ntiles, 256, 0, s>>>(g, t, p, F.f[1], F.u, F.nbr, F.f[0]); break;
-    case 512: k_r1_coef<512><<<t.ntiles, 512, 0, s>>>(g, t, p, F.f[1], F.u, F.nbr, F.f[0]); break;
-    default: return hipErrorInvalidValue;
-    }
+    (void)t;
+    const PhaseTiling pt = phase_tiling(g, 64, 8);
+    k_r1_coef<64, 8><<<pt.ntiles, 512, 0, s>>>(g, pt, p, F.f[1], F.u, F.nbr, F.f[0]);
     return hipGetLastError();
 }
 
