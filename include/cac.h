@@ -225,7 +225,9 @@ cac_status cac_debug_substep(cac_handle *h, int which);
  * (previous ghosts; after P the phase field before the correction), 2 = u (3N),
  * 3 = populations of the current parity (27N), 4 = populations of the other
  * parity (after H the post-collision populations, 27N), 5 = compressive flux
- * on wall nodes (3N).  Errors: CAC_ERR_ARG (unknown buffer). */
+ * on wall nodes (3N).  With collision = 1: 3 = the post-collision populations
+ * rebuilt by the last H substep, 4 = the record planes (p*, a, omega, then
+ * unused planes), 27N each.  Errors: CAC_ERR_ARG (unknown buffer). */
 cac_status cac_debug_buffer(cac_handle *h, int which, float *d_out);
 
 /* Release the handle and the device memory it allocated itself. */

@@ -754,8 +754,9 @@ cac_status cac_debug_buffer(cac_handle *h, int which, float *d_out)
     case 0: src = h->F.phi[c]; break;
     case 1: src = h->F.phi[c ^ 1]; break;
     case 2: src = h->F.u; n = 3 * N; break;
-    case 3: src = h->F.f[c]; n = 27 * N; break;
-    case 4: src = h->F.f[c ^ 1]; n = 27 * N; break;
+    // collision = 1: the rebuilt populations and the record planes, whatever the parity
+    case 3: src = h->F.f[h->prm.collision == 1 ? 0 : c]; n = 27 * N; break;
+    case 4: src = h->F.f[h->prm.collision == 1 ? 1 : c ^ 1]; n = 27 * N; break;
     case 5: src = h->F.a; n = 3 * N; break;
     default: return fail(h, CAC_ERR_ARG, "buffer %d", which);
     }

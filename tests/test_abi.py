@@ -48,6 +48,7 @@ def test_default_params_match_workloads(lib):
             assert list(p.g) == list(v)
         else:
             assert getattr(p, k) == pytest.approx(v), k
+    assert p.collision == 0  # local-moment collision unless asked
 
 
 def test_init_rejects_bad_arguments(lib):
@@ -59,6 +60,9 @@ def test_init_rejects_bad_arguments(lib):
     assert lib.cac_init(C.byref(h), 1024, 1024, 1024, C.byref(p), cb, None, None) == capi.CAC_ERR_ARG
     # 27 N must fit in 32 bits (543^3 does not; 512^3 does)
     assert lib.cac_init(C.byref(h), 543, 543, 543, C.byref(p), cb, None, None) == capi.CAC_ERR_ARG
+    p.collision = 2  # only 0 (local moment) and 1 (gradient form) exist
+    assert lib.cac_init(C.byref(h), 8, 8, 8, C.byref(p), cb, None, None) == capi.CAC_ERR_ARG
+    p.collision = 0
     p.delta = 0.0
     assert lib.cac_init(C.byref(h), 8, 8, 8, C.byref(p), cb, None, None) == capi.CAC_ERR_ARG
     assert lib.cac_init(None, 8, 8, 8, C.byref(p), cb, None, None) == capi.CAC_ERR_ARG
