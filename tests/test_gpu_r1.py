@@ -10,6 +10,8 @@ Eq. (15), and pulls them.  Checked here:
   and u within 1e-4 of max |u| (the plain step's bar); the same on ragged tiles,
   at density ratio 1000 with an initial velocity field, and at the full
   256 x 256 x 128 size in the benchmark's launch;
+* the populations the rebuild kernel writes against the oracle's post-collision
+  populations of the previous step (1e-5 of their maximum);
 * bitwise: repeated runs, graph replay against eager launches, save / load /
   resume, NaN poisoning of never-read data and reverse workgroup order;
 * refusals: population export, adjoint, batches.
@@ -141,6 +143,28 @@ def test_r1_full_size_spreading(orc):
     w = W.spreading_256(0)
     print(f"[r1] full size {w.name} N={w.N}", flush=True)
     _cmp(gpu_run(w, 3, launch=tuning.launch_for(w.shape)), oracle_run(orc, w, 3), w, orc, 2e-6, 1e-5)
+
+
+@pytest.mark.parametrize("steps", [2, 6])
+def test_r1_rebuilt_populations(orc, steps):
+    """The populations the rebuild kernel writes in step n are the post-collision
+    populations of step n - 1: against the oracle's, on every fluid node, within
+    1e-5 of their maximum."""
+    w = _variable_density_case()
+    s = _sim(w)
+    s.step(steps)
+    fg = s.debug_buffer(3).cpu().numpy().astype(np.float64).reshape(27, w.N)
+    s.sync()
+    s.close()
+    o = orc.OracleSim.create(w.shape, w.solid, w.theta.astype(np.float64), orc.Params(**_params(w)),
+                             w.phi0.astype(np.float64))
+    fo = np.zeros(27 * w.N)
+    o.step(steps - 1, fpost=fo)
+    fo = fo.reshape(27, w.N)
+    fl = w.solid == 0
+    err = np.abs(fg - fo)[:, fl].max() / np.abs(fo[:, fl]).max()
+    print(f"[r1] rebuilt populations after {steps} steps: {err:.2e} of max |f*|", flush=True)
+    assert err <= 1e-5
 
 
 def test_r1_uniform_flow_stays_uniform():
