@@ -22,14 +22,19 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("case", sorted(CASES))
-def test_geometry_parity(orc, case):
+@pytest.mark.parametrize("case,collision", [(c, 0) for c in sorted(CASES)] +
+                         [("sphere", 1), ("rough", 1), ("porous_contrast", 1)])
+def test_geometry_parity(orc, case, collision):
+    """collision = 1: the gradient-form collision, whose velocity stencil meets
+    the curved and porous walls (u = 0 on solid nodes)."""
     from paper_2607_25444_amd import capi
     make, extra = CASES[case]
     w = make()
     prm = dict(w.params)
     prm.update(extra)
-    print(f"[geometry] {case} {w.name} walls={int((w.solid == 1).sum())} steps={STEPS}", flush=True)
+    prm["collision"] = collision
+    print(f"[geometry] {case} collision={collision} {w.name} walls={int((w.solid == 1).sum())} steps={STEPS}",
+          flush=True)
     s = capi.Sim(w.shape, prm)
     s.set_geometry(w.solid, w.theta)
     s.set_state(w.phi0)
