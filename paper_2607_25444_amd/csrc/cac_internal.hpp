@@ -154,7 +154,7 @@ hipError_t launch_hydro(const Grid &g, const Tiling &t, const DevParams &p, cons
 // field into F.f[0]; then pull, moments and collision into the record and u
 // (self = the first step after the state is set: each node pulls its own
 // equilibrium).
-hipError_t launch_r1_coef(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, hipStream_t s);
+hipError_t launch_r1_rebuild(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, hipStream_t s);
 hipError_t launch_r1_stream(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, int pcur, bool self,
                             hipStream_t s);
 hipError_t launch_phase(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, int pcur,

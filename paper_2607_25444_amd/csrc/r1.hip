@@ -5,7 +5,7 @@
 // No populations are kept from one step to the next.  The state of a node is
 // its record (p*, u, a, omega) of the last collision.  A step takes two
 // kernels:
-//   k_r1_coef    A2 = -(c_s^2/omega)(grad u + grad u^T) (Eq. (15)) from the
+//   k_r1_rebuild A2 = -(c_s^2/omega)(grad u + grad u^T) (Eq. (15)) from the
 //                isotropic stencil (Eq. (22)) of the stored velocity field
 //                (u = 0 on solid nodes; the planes staged through LDS in
 //                column tiles), then the node's post-collision
@@ -20,7 +20,7 @@
 // Rebuilding each population at the pulling node instead (from the 17
 // Hermite coefficients of its source, 68 bytes per node) needs 314 gathers
 // per node against 27 here; on gfx950 that substep took 1.49 ms against
-// 0.57 ms on 256 x 256 x 128.
+// 0.49 ms here on 256 x 256 x 128.
 //
 // Layout (structure of arrays, node index n):
 //   rebuilt populations P[i*N + n] (27 planes) in the first population buffer;
@@ -135,7 +135,7 @@ __device__ __forceinline__ void r1_stream_node(const Grid &g, const DevParams &p
 // takes part in the loads and both barriers of each plane; threads outside the
 // grid skip only the node update.
 template <int CX, int CY>
-__global__ __launch_bounds__(CX *CY) void k_r1_coef(Grid g, PhaseTiling pt, DevParams p, const float *__restrict__ rec,
+__global__ __launch_bounds__(CX *CY) void k_r1_rebuild(Grid g, PhaseTiling pt, DevParams p, const float *__restrict__ rec,
                                                     const float *__restrict__ u, const uint32_t *__restrict__ nbr,
                                                     float *__restrict__ fout)
 {
@@ -211,11 +211,11 @@ __global__ __launch_bounds__(NT) void k_r1_stream(Grid g, Tiling t, DevParams p,
 
 // The rebuilt populations live in the first population buffer, the record in
 // the second.
-hipError_t launch_r1_coef(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, hipStream_t s)
+hipError_t launch_r1_rebuild(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, hipStream_t s)
 {
     (void)t;
     const PhaseTiling pt = phase_tiling(g, 64, 8);
-    k_r1_coef<64, 8><<<pt.ntiles, 512, 0, s>>>(g, pt, p, F.f[1], F.u, F.nbr, F.f[0]);
+    k_r1_rebuild<64, 8><<<pt.ntiles, 512, 0, s>>>(g, pt, p, F.f[1], F.u, F.nbr, F.f[0]);
     return hipGetLastError();
 }
 

@@ -186,7 +186,7 @@ hipError_t launch_h(cac_handle *h, int c)
     if (h->prm.collision == 0) return launch_hydro(h->g, h->t, h->dp, h->F, c, c, h->stream);
     // gradient form: the first step after the state is set pulls each node's own equilibrium
     if (h->steps > 0) {
-        const hipError_t e = launch_r1_coef(h->g, h->t, h->dp, h->F, h->stream);
+        const hipError_t e = launch_r1_rebuild(h->g, h->t, h->dp, h->F, h->stream);
         if (e != hipSuccess) return e;
     }
     return launch_r1_stream(h->g, h->t, h->dp, h->F, c, h->steps == 0, h->stream);
