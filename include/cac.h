@@ -77,9 +77,9 @@ typedef struct {
                                 1 -> the gradient form of Eq. (15), -(c_s^2/omega)(grad u + grad u^T),
                                      from the isotropic stencil of Eq. (22) with u = 0 on solid nodes
                                      (the thread-safe formulation of Sec. II A: no populations are
-                                     stored between steps).  With 1, cac_get_populations, the
-                                     adjoint (cac_tape_*, cac_adjoint) and batches are refused
-                                     with CAC_ERR_STATE / CAC_ERR_ARG. */
+                                     stored between steps).  With 1, cac_get_populations and the
+                                     adjoint (cac_tape_*, cac_adjoint) are refused with
+                                     CAC_ERR_STATE; a batch takes it when all its domains do. */
 } cac_params;
 
 /* Fill p with the defaults (rho = 1, nu = 0.04, sigma = 0.02, delta = 4,
@@ -302,8 +302,9 @@ typedef struct {
 
 /* Create a batch of ndom (1..65535) domains on the current device, geometry
  * and initial state included (populations at rest equilibrium, M_target per
- * domain in FP64).  The total 27 * sum(N) must fit in 31 bits.  Errors:
- * CAC_ERR_ARG (sizes, parameters, null pointers), CAC_ERR_ALLOC, CAC_ERR_HIP. */
+ * domain in FP64).  The total 27 * sum(N) must fit in 31 bits.  All domains
+ * share one params.collision setting.  Errors: CAC_ERR_ARG (sizes, parameters,
+ * null pointers, mixed collision settings), CAC_ERR_ALLOC, CAC_ERR_HIP. */
 cac_status cac_batch_init(cac_batch **b, int ndom, const cac_domain_desc *d, cac_alloc_fn alloc, void *alloc_user,
                           void *hip_stream);
 

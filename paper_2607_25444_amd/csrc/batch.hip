@@ -7,6 +7,8 @@
 // domain's slice of the concatenated arrays.  Volume sums are kept per domain
 // (partial index = the domain's first partial + its tile), so the FP64 totals
 // do not depend on the schedule.
+#include "batch_r1.hpp"
+#include "r1_device.hpp"
 #include "step_device.hpp"
 
 namespace cac {
@@ -206,6 +208,78 @@ __global__ __launch_bounds__(256) void k_bvol_apply(BatchPtrs B, const BatchDoma
         if (!s[k] && v[k] > eps && v[k] < 1.0f - eps)
             phi[n] = (float)((double)v[k] + lam * ((double)v[k] * (1.0 - (double)v[k])));
     }
+}
+
+// ------------------------------------------------------------------ gradient form
+// collision = 1 (all domains of the batch): the record of each domain in its
+// slice of the second population buffer, its rebuilt populations in the first.
+
+template <int BX, int BY>
+__global__ __launch_bounds__(BX *BY) void k_br1_rebuild(BatchPtrs B, const BatchDomain *__restrict__ dom,
+                                                        const uint2 *__restrict__ items)
+{
+    const uint2 dt = items[blockIdx.x];
+    const BatchDomain d = dom[dt.x];
+    r1_rebuild_tile<BX, BY>(d.g, d.pt, dt.y, B.f[1] + 27u * d.off, B.u + 3u * d.off, B.nbr + d.off,
+                            B.f[0] + 27u * d.off);
+}
+
+template <int NT, bool SELF>
+__global__ __launch_bounds__(NT) void k_br1_stream(BatchPtrs B, const BatchDomain *__restrict__ dom,
+                                                   const uint2 *__restrict__ items, const float *__restrict__ pstar0,
+                                                   int cur)
+{
+    const uint2 dt = items[blockIdx.x];
+    const BatchDomain d = dom[dt.x];
+    const Node nd = tile_node(d.g, d.t, dt.y);
+    const float *fin = B.f[0] + 27u * d.off;
+    const float *phi = (cur ? B.phi[1] : B.phi[0]) + d.off;
+    float *rec = B.f[1] + 27u * d.off;
+    if (d.t.bx >= d.g.nx)
+        r1_stream_node<SELF, true>(d.g, d.p, nd, fin, phi, B.nbr + d.off, pstar0 + d.off, B.u + 3u * d.off, rec,
+                                   B.flag);
+    else
+        r1_stream_node<SELF, false>(d.g, d.p, nd, fin, phi, B.nbr + d.off, pstar0 + d.off, B.u + 3u * d.off, rec,
+                                    B.flag);
+}
+
+hipError_t launch_br1_rebuild(const BatchPtrs &B, int code, const uint2 *items, uint32_t nitems, hipStream_t s)
+{
+    if (!nitems) return hipSuccess;
+    int bx, by;
+    phase_shape_of(code, bx, by);
+#define CAC_BR1R(BX_, BY_)                                                        \
+    if (bx == BX_ && by == BY_) {                                                 \
+        k_br1_rebuild<BX_, BY_><<<nitems, BX_ * BY_, 0, s>>>(B, B.dom, items);    \
+        return hipGetLastError();                                                 \
+    }
+    CAC_BR1R(64, 8)
+    CAC_BR1R(64, 4)
+    CAC_BR1R(32, 8)
+    CAC_BR1R(32, 16)
+    CAC_BR1R(16, 16)
+    CAC_BR1R(128, 4)
+#undef CAC_BR1R
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_br1_stream(const BatchPtrs &B, const float *pstar0, int nt, const uint2 *items, uint32_t nitems,
+                             int cur, bool self, hipStream_t s)
+{
+    if (!nitems) return hipSuccess;
+#define CAC_BR1S(NT_)                                                                        \
+    if (self)                                                                                \
+        k_br1_stream<NT_, true><<<nitems, NT_, 0, s>>>(B, B.dom, items, pstar0, cur);       \
+    else                                                                                     \
+        k_br1_stream<NT_, false><<<nitems, NT_, 0, s>>>(B, B.dom, items, pstar0, cur);
+    switch (nt) {
+    case 128: CAC_BR1S(128) break;
+    case 256: CAC_BR1S(256) break;
+    case 512: CAC_BR1S(512) break;
+    default: return hipErrorInvalidValue;
+    }
+#undef CAC_BR1S
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ launchers

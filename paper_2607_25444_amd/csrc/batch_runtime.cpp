@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "batch_r1.hpp"
 #include "../../include/cac.h"
 #include "cac_internal.hpp"
 
@@ -60,6 +61,7 @@ struct cac_batch {
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int cur = 0;
     long long steps = 0;
+    int coll = 0;  // collision reading of every domain (cac_params.collision)
     std::string err;
 };
 
@@ -200,12 +202,20 @@ cac_status apply_schedule(cac_batch *b, const Schedule &s)
     return CAC_OK;
 }
 
-cac_status run_bstep(cac_batch *b, hipStream_t s)
+// self: the first step of a gradient-form batch (each node pulls its own
+// equilibrium); never captured in a graph.
+cac_status run_bstep(cac_batch *b, hipStream_t s, bool self = false)
 {
     const int c = b->cur;
     const int nt = sched_nt(b->sch);
     BCHK(b, launch_bghost(b->B, b->nwall, c, s));
-    BCHK(b, launch_bhydro(b->B, nt, b->d_hitems, b->nh, b->hgrid, c, s));
+    if (b->coll) {
+        // one workgroup per item whatever the grid multiplier
+        if (!self) BCHK(b, launch_br1_rebuild(b->B, b->sch.phase, b->d_pitems, b->np, s));
+        BCHK(b, launch_br1_stream(b->B, b->pstar0, nt, b->d_hitems, b->nh, c, self, s));
+    } else {
+        BCHK(b, launch_bhydro(b->B, nt, b->d_hitems, b->nh, b->hgrid, c, s));
+    }
     BCHK(b, launch_bphase(b->B, b->sch.phase, b->d_pitems, b->np, b->pgrid, c, s));
     BCHK(b, launch_bvolume(b->B, nt, b->d_hitems, b->nh, b->hgrid, c ^ 1, s));
     return CAC_OK;
@@ -261,7 +271,8 @@ cac_status snapshot(cac_batch *b, float *buf, bool save)
     struct Part {
         float *p;
         size_t n;
-    } parts[] = {{b->B.f[b->cur], 27 * N}, {b->B.phi[0], N}, {b->B.phi[1], N}, {b->B.u, 3 * N}, {b->B.a, 3 * N}};
+    } parts[] = {{b->coll ? b->B.f[1] : b->B.f[b->cur], 27 * N}, {b->B.phi[0], N}, {b->B.phi[1], N}, {b->B.u, 3 * N},
+                 {b->B.a, 3 * N}};
     size_t o = 0;
     for (auto &pt : parts) {
         if (save)
@@ -356,7 +367,7 @@ cac_status cac_batch_init(cac_batch **bp, int ndom, const cac_domain_desc *d, ca
     unsigned long long Ntot = 0;
     for (int k = 0; k < ndom; ++k) {
         if (d[k].nx < 2 || d[k].ny < 2 || d[k].nz < 2 || !d[k].solid || !d[k].d_phi0 || !valid_params(d[k].params) ||
-            d[k].params.collision != 0)
+            d[k].params.collision != d[0].params.collision)
             return CAC_ERR_ARG;
         Ntot += (unsigned long long)d[k].nx * d[k].ny * d[k].nz;
     }
@@ -367,6 +378,7 @@ cac_status cac_batch_init(cac_batch **bp, int ndom, const cac_domain_desc *d, ca
     b->alloc_user = alloc_user;
     b->ndom = ndom;
     b->Ntot = (uint32_t)Ntot;
+    b->coll = d[0].params.collision;
     auto bail = [&](cac_status st) {
         for (void *q : b->owned) (void)hipFree(q);
         delete b;
@@ -534,14 +546,15 @@ cac_status cac_batch_step(cac_batch *b, int nsteps)
     if (!b) return CAC_ERR_ARG;
     if (nsteps < 0) return bfail(b, CAC_ERR_ARG, "nsteps < 0");
     for (int k = 0; k < nsteps; ++k) {
-        if (b->use_graph) {
+        const bool self = b->coll && b->steps == 0;
+        if (b->use_graph && !self) {
             if (!b->gexec[b->cur]) {
                 cac_status st = capture(b, b->cur);
                 if (st != CAC_OK) return st;
             }
             BCHK(b, hipGraphLaunch(b->gexec[b->cur], b->stream));
         } else {
-            cac_status st = run_bstep(b, b->stream);
+            cac_status st = run_bstep(b, b->stream, self);
             if (st != CAC_OK) return st;
         }
         b->cur ^= 1;
@@ -580,7 +593,10 @@ cac_status cac_batch_get_fields(cac_batch *b, int k, float *d_phi, float *d_u, f
     if (!b || k < 0 || k >= b->ndom) return CAC_ERR_ARG;
     const Fields F = domain_fields(b, k);
     const Grid &g = b->dom[k].g;
-    if (d_phi || d_pstar) BCHK(b, launch_gather(g, F, b->cur, b->cur, b->steps > 0, 27, d_phi, d_pstar, b->stream));
+    // p*: the post-collision populations' zeroth moment, or the record's p* plane (collision = 1)
+    if (d_phi || d_pstar)
+        BCHK(b, launch_gather(g, F, b->coll ? 1 : b->cur, b->cur, b->steps > 0, b->coll ? 1 : 27, d_phi, d_pstar,
+                              b->stream));
     if (d_u) BCHK(b, hipMemcpyAsync(d_u, F.u, 3 * (size_t)g.N * sizeof(float), hipMemcpyDeviceToDevice, b->stream));
     return CAC_OK;
 }
@@ -613,7 +629,13 @@ cac_status cac_batch_profile(cac_batch *b, int nsteps, double *ms)
         BCHK(b, hipEventRecord(e[0], b->stream));
         BCHK(b, launch_bghost(b->B, b->nwall, c, b->stream));
         BCHK(b, hipEventRecord(e[1], b->stream));
-        BCHK(b, launch_bhydro(b->B, nt, b->d_hitems, b->nh, b->hgrid, c, b->stream));
+        if (b->coll) {
+            const bool self = b->steps == 0;
+            if (!self) BCHK(b, launch_br1_rebuild(b->B, b->sch.phase, b->d_pitems, b->np, b->stream));
+            BCHK(b, launch_br1_stream(b->B, b->pstar0, nt, b->d_hitems, b->nh, c, self, b->stream));
+        } else {
+            BCHK(b, launch_bhydro(b->B, nt, b->d_hitems, b->nh, b->hgrid, c, b->stream));
+        }
         BCHK(b, hipEventRecord(e[2], b->stream));
         BCHK(b, launch_bphase(b->B, b->sch.phase, b->d_pitems, b->np, b->pgrid, c, b->stream));
         BCHK(b, hipEventRecord(e[3], b->stream));
@@ -662,7 +684,8 @@ cac_status cac_batch_autotune(cac_batch *b, const char *cache_path, int trial_st
     auto trial = [&](const Schedule &s, double &ms) -> cac_status {
         cac_status r = apply_schedule(b, s);
         if (r != CAC_OK) return r;
-        r = run_bstep(b, b->stream);
+        // warm-up step (the first gradient-form step pulls the equilibrium); the timed ones are ordinary
+        r = run_bstep(b, b->stream, b->coll && b->steps == 0);
         if (r != CAC_OK) return r;
         b->cur ^= 1;
         BCHK(b, hipEventRecord(e0, b->stream));

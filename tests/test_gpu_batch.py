@@ -1,6 +1,7 @@
 """Batched persistent step (libcac cac_batch_*) on the GPU: every domain equals
 the same domain advanced alone, and the FP64 oracle; schedules, graph replay
-and the autotuner leave results unchanged."""
+and the autotuner leave results unchanged.  The same for batches with the
+gradient-form collision (collision = 1)."""
 import numpy as np
 import pytest
 
@@ -168,3 +169,80 @@ def test_batch_watchdog():
         b.sync()
     assert e.value.status == capi.CAC_ERR_NONFINITE
     b.close()
+
+
+# ------------------------------------------------------------------ gradient form
+
+def _gradient_form(ws):
+    return [W.Workload(w.name, w.shape, w.solid, w.theta, w.phi0, dict(w.params, collision=1), 0) for w in ws]
+
+
+@pytest.mark.parametrize("sched", [None, (32, 4, 2, 3, 2, 0, 1), (0, 512, 0, 5, 0, 1, 1), (16, 16, 1, 2, 8, 1, 0)])
+def test_batch_gradient_form_equals_single_domains(sched):
+    """collision = 1 in every domain: each domain equals the same domain advanced
+    alone with the gradient-form collision, for fitted and fixed tiles, every
+    phase tile shape used here, persistent grid multipliers, and graph replay
+    or eager launches (the first step, which pulls each node's equilibrium, is
+    launched outside the graph)."""
+    from paper_2607_25444_amd import capi
+    ws = _gradient_form(_domains())
+    b = capi.Batch(ws)
+    if sched:
+        b.set_schedule(*sched)
+    b.step(15)
+    for k, w in enumerate(ws):
+        phi_b, u_b = _batch_fields(b, k)
+        phi_s, u_s = _single(w, 15)
+        fl = w.solid == 0
+        assert np.abs(phi_b - phi_s)[fl].max() <= 2e-6
+        assert np.abs(u_b - u_s).max() <= 2e-5 * max(np.abs(u_s).max(), 1e-9) + 1e-12
+    b.close()
+
+
+def test_batch_gradient_form_against_oracle(orc):
+    from paper_2607_25444_amd import capi
+    ws = _gradient_form(_domains()[:3])
+    b = capi.Batch(ws)
+    b.step(10)
+    for k, w in enumerate(ws):
+        phi_b, u_b = _batch_fields(b, k)
+        ps_b = b.fields(k)[2].cpu().numpy().astype(np.float64)
+        o = orc.OracleSim.create(w.shape, w.solid, w.theta.astype(np.float64), orc.Params(**w.params),
+                                 w.phi0.astype(np.float64))
+        o.step(10)
+        fl = w.solid == 0
+        assert np.abs(phi_b - o.phi)[fl].max() <= 5e-6
+        uo = o.u.reshape(3, -1)[:, fl]
+        assert np.abs(u_b.reshape(3, -1)[:, fl] - uo).max() <= 5e-5 * np.abs(uo).max()
+        assert np.abs(ps_b - o.pstar)[fl].max() <= 5e-5 * max(np.abs(o.pstar[fl]).max(), np.abs(uo).max(), 1e-4)
+    b.close()
+
+
+def test_batch_gradient_form_autotune_and_mixed_batches():
+    """The autotuner keeps the state of a gradient-form batch, from its first
+    step on; a batch mixing the two collision readings is refused."""
+    from paper_2607_25444_amd import capi
+    ws = _gradient_form(_domains())
+    a = capi.Batch(ws)
+    assert a.autotune(None, trial_steps=2) > 0  # tuned before the first step
+    a.step(6)
+    ref = capi.Batch(ws)
+    ref.step(6)
+    for k in range(len(ws)):
+        p0, u0 = _batch_fields(ref, k)
+        p1, u1 = _batch_fields(a, k)
+        assert np.abs(p0 - p1).max() <= 2e-6
+        assert np.abs(u0 - u1).max() <= 2e-5 * max(np.abs(u0).max(), 1e-9) + 1e-12
+    before = [_batch_fields(a, k) for k in range(len(ws))]
+    a.autotune(None, trial_steps=2)
+    after = [_batch_fields(a, k) for k in range(len(ws))]
+    for (p0, u0), (p1, u1) in zip(before, after):
+        np.testing.assert_array_equal(p0, p1)
+        np.testing.assert_array_equal(u0, u1)
+    a.step(2)
+    a.sync()
+    a.close()
+    ref.close()
+    mixed = _domains()[:1] + ws[1:2]
+    with pytest.raises(capi.CacError):
+        capi.Batch(mixed)

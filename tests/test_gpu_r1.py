@@ -14,7 +14,7 @@ Eq. (15), and pulls them.  Checked here:
   populations of the previous step (1e-5 of their maximum);
 * bitwise: repeated runs, graph replay against eager launches, save / load /
   resume, NaN poisoning of never-read data and reverse workgroup order;
-* refusals: population export, adjoint, batches.
+* refusals: population export, adjoint (batches: tests/test_gpu_batch.py).
 """
 import numpy as np
 import pytest
@@ -258,7 +258,7 @@ def test_r1_poison_and_reverse_order():
 
 
 def test_r1_refusals():
-    """No populations to export, no adjoint, no batches with collision = 1."""
+    """No populations to export and no adjoint with collision = 1."""
     from paper_2607_25444_amd import capi
     w = W.sessile((24, 20, 16), 5.0, 60.0)
     s = _sim(w)
@@ -270,6 +270,3 @@ def test_r1_refusals():
         s.tape_forward(4, 2)
     assert e.value.status == capi.CAC_ERR_STATE
     s.close()
-    w2 = W.Workload(w.name, w.shape, w.solid, w.theta, w.phi0, _params(w), 0)
-    with pytest.raises(capi.CacError):
-        capi.Batch([w2])
