@@ -75,7 +75,8 @@ typedef struct {
     int collision;           /* non-equilibrium moment A2 of the regularised populations, Eq. (14):
                                 0 -> the local second moment of the pre-collision populations;
                                 1 -> the gradient form of Eq. (15), -(c_s^2/omega)(grad u + grad u^T),
-                                     from the isotropic stencil of Eq. (22) with u = 0 on solid nodes
+                                     from the isotropic stencil of Eq. (22), a solid neighbour
+                                     holding the node's mirror image -u (zero at the half-link)
                                      (the thread-safe formulation of Sec. II A: no populations are
                                      stored between steps).  With 1, cac_get_populations and the
                                      adjoint (cac_tape_*, cac_adjoint) are refused with

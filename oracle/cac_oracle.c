@@ -503,9 +503,10 @@ int orc_ghost(const orc_params *p, int nx, int ny, int nz, const uint8_t *solid,
 /* Gradient form of the non-equilibrium moment, Eq. (15), at every fluid node:
  *   A2_ab = -(c_s^2/omega) (d_a u_b + d_b u_a),
  * with the velocity derivatives taken by the isotropic gradient of Eq. (22)
- * applied to each velocity component.  Reading: u = 0 on solid nodes (the
- * walls are at rest).  u: 3 planes of N; omega: N; A2: 9 planes of N
- * (row-major a, b), zero on solid nodes. */
+ * applied to each velocity component.  Reading: a solid neighbour x + c_i of
+ * node x holds the mirror image -u(x), so that the velocity vanishes at the
+ * half-link, where halfway bounce-back puts the resting wall.  u: 3 planes of
+ * N; omega: N; A2: 9 planes of N (row-major a, b), zero on solid nodes. */
 void orc_a2grad(int nx, int ny, int nz, const uint8_t *solid, const double *u, const double *omega, double *A2)
 {
     dims_t g = {nx, ny, nz, (long)nx * ny * nz};
@@ -517,9 +518,11 @@ void orc_a2grad(int nx, int ny, int nz, const uint8_t *solid, const double *u, c
         double D[3][3] = {{0}}; /* D[b][a] = d_b u_a */
         for (int i = 0; i < Q; ++i) {
             long y = neighbour(&g, n, i);
-            if (solid[y]) continue;
             for (int b = 0; b < 3; ++b)
-                for (int a = 0; a < 3; ++a) D[b][a] += weight(i) * CV[i][b] * u[a * N + y] / CS2;
+                for (int a = 0; a < 3; ++a) {
+                    const double ua = solid[y] ? -u[a * N + n] : u[a * N + y];
+                    D[b][a] += weight(i) * CV[i][b] * ua / CS2;
+                }
         }
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) A2[(3 * a + b) * N + n] = -(CS2 / omega[n]) * (D[a][b] + D[b][a]);

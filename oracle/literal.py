@@ -9,7 +9,8 @@ lattice tables and wall geometry) in whole-array form: periodic shifts with
 ghosts, A2 as the moment of f - f^eq + S/2, forces as accelerations,
 bounce-back, zero advective flux at wall faces, the wall compressive-flux
 switch, and the switch ``collision`` = 1 that takes A2 in the gradient form
-of Eq. (15) from the new velocity field, zero on solid nodes).  Non-smooth points (minmod, upwind, the chi band, the normal guard,
+of Eq. (15) from the new velocity field, a solid neighbour holding the mirror
+image -u of the node).  Non-smooth points (minmod, upwind, the chi band, the normal guard,
 lambda_s at 0, the cot regularisation) follow the branch the forward pass
 takes; ``torch.where`` selections and guarded square roots keep gradients
 finite.
@@ -245,8 +246,11 @@ def hydro(p, solid, phi_hat, f):
     u_all = torch.zeros((3, N), dtype=DT).index_copy(1, idx, u).reshape((3,) + tuple(shp))
     if p.get("collision", 0) == 1:
         # gradient form, Eq. (15): A2_ab = -(c_s^2/omega)(d_a u_b + d_b u_a), the
-        # derivatives by Eq. (22) on the new velocity field (zero on solid nodes)
-        D = torch.stack([grad_iso(u_all[c]).reshape(3, N)[:, idx] for c in range(3)], 1)  # D[b, a] = d_b u_a
+        # derivatives by Eq. (22) on the new velocity field; a solid neighbour holds
+        # the mirror image -u of the node, i.e. the stencil of the field that is zero
+        # on solids minus u(x) times the stencil of the solid indicator
+        gs = grad_iso(solid.to(DT)).reshape(3, N)[:, idx]
+        D = torch.stack([grad_iso(u_all[c]).reshape(3, N)[:, idx] - u[c] * gs for c in range(3)], 1)  # D[b, a] = d_b u_a
         A2 = -(CS2 / omega) * (D + D.transpose(0, 1))
     else:
         A2 = torch.einsum("ia,ib,in->abn", CV, CV, ff - fe + 0.5 * S)

@@ -223,7 +223,8 @@ def hydro(params, shape, solid, phi_hat, f_in):
 
 def a2grad(shape, solid, u, omega):
     """Gradient form of the non-equilibrium moment, Eq. (15), at every fluid
-    node (u = 0 on solid nodes): returns 9 planes of N, row-major (a, b)."""
+    node (a solid neighbour holds the mirror image -u of the node): returns 9
+    planes of N, row-major (a, b)."""
     nx, ny, nz = shape
     N = nx * ny * nz
     solid = np.ascontiguousarray(solid, dtype=np.uint8).reshape(-1)

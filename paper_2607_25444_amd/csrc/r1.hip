@@ -7,9 +7,10 @@
 // kernels:
 //   k_r1_rebuild A2 = -(c_s^2/omega)(grad u + grad u^T) (Eq. (15)) from the
 //                isotropic stencil (Eq. (22)) of the stored velocity field
-//                (u = 0 on solid nodes; the planes staged through LDS in
-//                column tiles), then the node's post-collision
-//                populations (Eqs. (3), (11), (14), (16), (17)), written once;
+//                (a solid neighbour holds the node's mirror image -u; the
+//                planes staged through LDS in column tiles), then the node's
+//                post-collision populations (Eqs. (3), (11), (14), (16),
+//                (17)), written once;
 //   k_r1_stream  pull f_i(x) = f*_i(x - c_i) (halfway bounce-back: f*_opp(i)
 //                of x itself), the kinetic moments, forces and velocity of
 //                the collision at x (Eqs. (6)-(10), (18)-(21)); writes the

@@ -10,7 +10,8 @@ namespace cac {
 
 // Gradient form of the non-equilibrium moment at fluid node n (solid-neighbour
 // mask m) from its velocity stencil s*[k], k = (dz+1)*9 + (dy+1)*3 + (dx+1),
-// already zero on solid neighbours; then its post-collision populations
+// in which solid neighbours already hold the mirror image -u of the node;
+// then its post-collision populations
 // (non-temporal stores: read once, by the pull).
 __device__ __forceinline__ void r1_rebuild(uint32_t N, uint32_t n, const float (&sx)[27], const float (&sy)[27],
                                            const float (&sz)[27], const float *__restrict__ rec,
@@ -147,6 +148,8 @@ __device__ __forceinline__ void r1_rebuild_tile(const Grid &g, const PhaseTiling
             const uint32_t m = nbr[n];
             if (!(m & 1u)) {
                 const int sl[3] = {k % 3, (k + 1) % 3, (k + 2) % 3};
+                const int qc = (lx + 1) + LX * (ly + 1);
+                const float cx0 = su[sl[1]][0][qc], cy0 = su[sl[1]][1][qc], cz0 = su[sl[1]][2][qc];
                 float sx[27], sy[27], sz[27];
                 static_for<27>([&](auto J) {
                     constexpr int kk = J;
@@ -154,12 +157,13 @@ __device__ __forceinline__ void r1_rebuild_tile(const Grid &g, const PhaseTiling
                     constexpr int li = Lat::idx(dx, dy, dz);
                     const int q = (lx + 1 + dx) + LX * (ly + 1 + dy);
                     const int sv = sl[dz + 1];
-                    // zero on solid neighbours (the walls are at rest)
+                    // a solid neighbour holds the mirror image -u of the node: the
+                    // velocity vanishes at the half-link, where bounce-back puts the wall
                     const bool sol = ((m >> li) & 1u) != 0u;
                     const float vx = su[sv][0][q], vy = su[sv][1][q], vz = su[sv][2][q];
-                    sx[kk] = sol ? 0.f : vx;
-                    sy[kk] = sol ? 0.f : vy;
-                    sz[kk] = sol ? 0.f : vz;
+                    sx[kk] = sol ? -cx0 : vx;
+                    sy[kk] = sol ? -cy0 : vy;
+                    sz[kk] = sol ? -cz0 : vz;
                 });
                 r1_rebuild(N, n, sx, sy, sz, rec, fout);
             }

@@ -26,7 +26,7 @@ CASES = {
                          [("sphere", 1), ("rough", 1), ("porous_contrast", 1)])
 def test_geometry_parity(orc, case, collision):
     """collision = 1: the gradient-form collision, whose velocity stencil meets
-    the curved and porous walls (u = 0 on solid nodes)."""
+    the curved and porous walls (a solid neighbour holds the node's mirror image -u)."""
     from paper_2607_25444_amd import capi
     make, extra = CASES[case]
     w = make()

@@ -2,12 +2,15 @@
 
 The non-equilibrium moment of the regularised populations, Eq. (14), is taken in
 the gradient form of Eq. (15), A2 = -(c_s^2/omega)(grad u + grad u^T), with the
-velocity derivatives from the isotropic stencil of Eq. (22) and u = 0 on solid
-nodes.  Pinned here against:
+velocity derivatives from the isotropic stencil of Eq. (22); a solid neighbour
+holds the mirror image -u of the node (zero velocity at the half-link, where
+halfway bounce-back puts the wall).  Pinned here against:
 * closed forms of the stencil on sinusoidal velocity fields (the isotropic
   derivative of sin(kx) is sin(k) cos(kx)) and on a uniform flow beside a wall;
 * the decay of a shear wave, which must tend to nu k^2 with
   nu = c_s^2 (1/omega - 1/2), Eq. (4), at second order in k;
+* force-driven channel flow between walls, which must tend to the parabola with
+  the walls at the half-links at second order in the width;
 * invariants: a uniform flow stays uniform; the fluid sum of p* is conserved;
 * the independent whole-array implementation in oracle/literal.py.
 """
@@ -46,8 +49,9 @@ def test_a2grad_sinusoid_closed_form(a, b):
 
 
 def test_a2grad_uniform_flow_beside_a_wall():
-    # u = (U, 0, 0) on fluid nodes, solid layer z = 0 (u = 0 there): next to the
-    # wall d_z u_x = (u(z+1) - u(z-1))/2 = +U/2 at z = 1 and -U/2 at z = nz - 1
+    # u = (U, 0, 0) on fluid nodes, solid layer z = 0 (holding the mirror image -U
+    # of each node beside it): d_z u_x = (u(z+1) - u(z-1))/2 = +U at z = 1 and -U
+    # at z = nz - 1 (the solid layer is its upper neighbour through the periodic wrap)
     shape = (6, 5, 7)
     nx, ny, nz = shape
     N = nx * ny * nz
@@ -60,8 +64,8 @@ def test_a2grad_uniform_flow_beside_a_wall():
     A2 = O.a2grad(shape, solid.reshape(-1), u.reshape(-1), om).reshape(3, 3, nz, ny, nx)
     om3 = om.reshape(nz, ny, nx)
     dz = np.zeros((nz, ny, nx))
-    dz[1] = U / 2
-    dz[nz - 1] = -U / 2
+    dz[1] = U
+    dz[nz - 1] = -U
     want = np.zeros((3, 3, nz, ny, nx))
     want[0, 2] = want[2, 0] = np.where(solid == 0, -(CS2 / om3) * dz, 0.0)
     np.testing.assert_allclose(A2, want, rtol=0, atol=1e-16)
@@ -155,3 +159,32 @@ def test_c_oracle_matches_literal():
     s0 = O.OracleSim.create(shape, solid.reshape(-1), theta, O.Params(**prm0), phi0)
     s0.step(6)
     assert np.abs(s0.u - s.u).max() > 1e-2 * np.abs(s0.u).max()
+
+
+def _channel_error(collision, H, nu=0.1, g=1e-5):
+    """Steady force-driven flow between two walls (solid layers z = 0 and H + 1,
+    fluid z = 1..H, periodic in x and y): max relative deviation from the
+    parabola u_x = a/(2 nu) (z - 1/2)(H + 1/2 - z), a = (rho - rho_g) g / rho,
+    whose zeros sit at the half-links where halfway bounce-back puts the walls."""
+    nz = H + 2
+    shape = (2, 2, nz)
+    N = 4 * nz
+    solid = np.zeros((nz, 2, 2), np.uint8)
+    solid[0] = solid[-1] = 1
+    prm = O.Params(nu_l=nu, nu_g=nu, rho_l=2.0, rho_g=1.0, g=(g, 0.0, 0.0), collision=collision)
+    s = O.OracleSim.create(shape, solid.reshape(-1), np.full(N, np.pi / 2), prm, np.ones(N))
+    s.step(int(6 * H * H / nu) + 1000)
+    z = np.arange(1, H + 1)
+    a = (2.0 - 1.0) / 2.0 * g
+    exact = a / (2.0 * nu) * (z - 0.5) * (H + 0.5 - z)
+    u = s.u.reshape(3, nz, 2, 2)[0, 1:H + 1, 0, 0]
+    return np.abs(u - exact).max() / exact.max()
+
+
+def test_channel_flow_converges_at_second_order():
+    e8, e16 = _channel_error(1, 8), _channel_error(1, 16)
+    assert e16 < 6e-3 and 3.0 < e8 / e16 < 5.0, (e8, e16)
+    # the local-moment collision too (this pins the halfway bounce-back and the
+    # forcing of both paths: a wall at the node would converge at first order)
+    r8, r16 = _channel_error(0, 8), _channel_error(0, 16)
+    assert r16 < 1.5e-3 and 3.0 < r8 / r16 < 5.0, (r8, r16)
