@@ -105,17 +105,22 @@ __device__ __forceinline__ void r1_stream_node(const Grid &g, const DevParams &p
 
 // Rebuild pass over column tile `tile` of CX x CY nodes marching through a z-chunk:
 // the velocity planes z-1, z, z+1 (with a one-node halo in x and y) sit in a
-// ring of three LDS slots, so each velocity value is loaded from memory about
-// (CX+2)(CY+2)/(CX CY) times per chunk instead of 27 times.  Every thread
-// takes part in the loads and both barriers of each plane; threads outside the
-// grid skip only the node update.
+// ring of four LDS slots, so each velocity value is loaded from memory about
+// (CX+2)(CY+2)/(CX CY) times per chunk instead of 27 times.  Plane z+2 is
+// fetched into registers while plane z is rebuilt and enters the ring at the
+// start of the next plane, one barrier per plane: the slot it overwrites held
+// plane z-2, which no wave still reads once every wave has passed the barrier
+// of plane z-1 -- a wave can only get here after that.  Every thread takes part
+// in the loads and the barriers; threads outside the grid skip only the node
+// update.
 template <int CX, int CY>
 __device__ __forceinline__ void r1_rebuild_tile(const Grid &g, const PhaseTiling &pt, uint32_t tile,
                                                 const float *__restrict__ rec, const float *__restrict__ u,
                                                 const uint32_t *__restrict__ nbr, float *__restrict__ fout)
 {
-    constexpr int LX = CX + 2, LP = (CX + 2) * (CY + 2);
-    __shared__ float su[3][3][LP];  // [slot][component][position]
+    constexpr int NT = CX * CY, LX = CX + 2, LP = (CX + 2) * (CY + 2);
+    constexpr int PQ = (LP + NT - 1) / NT;  // halo-plane points per thread
+    __shared__ float su[4][3][LP];          // [slot][component][position]
     const uint32_t txy = (uint32_t)pt.ntx * (uint32_t)pt.nty;
     const uint32_t zci = tile / txy, rxy = tile - zci * txy;
     const uint32_t tyi = rxy / (uint32_t)pt.ntx, txi = rxy - tyi * (uint32_t)pt.ntx;
@@ -126,28 +131,51 @@ __device__ __forceinline__ void r1_rebuild_tile(const Grid &g, const PhaseTiling
     const bool inxy = x < g.nx && y < g.ny;
     const uint32_t N = g.N;
 
-    auto load_plane = [&](int slot, int zg) {
+    // in-plane node offsets of this thread's halo-plane points (periodic wrap)
+    uint32_t qoff[PQ];
+#pragma unroll
+    for (int r = 0; r < PQ; ++r) {
+        const int q = tid + r * NT, qx = q % LX, qy = q / LX;
+        qoff[r] = q < LP ? (uint32_t)wrapc(x0 - 1 + qx, g.nx) + (uint32_t)wrapc(y0 - 1 + qy, g.ny) * (uint32_t)g.nx
+                         : 0u;
+    }
+    float pre[PQ][3];
+    auto fetch = [&](int zg) {
         const uint32_t zo = (uint32_t)wrapc(zg, g.nz) * g.nxny;
-        for (int q = tid; q < LP; q += CX * CY) {
-            const int qx = q % LX, qy = q / LX;
-            const uint32_t gi =
-                (uint32_t)wrapc(x0 - 1 + qx, g.nx) + (uint32_t)wrapc(y0 - 1 + qy, g.ny) * (uint32_t)g.nx + zo;
-            su[slot][0][q] = u[gi];
-            su[slot][1][q] = u[N + gi];
-            su[slot][2][q] = u[2u * N + gi];
-        }
+#pragma unroll
+        for (int r = 0; r < PQ; ++r)
+            if (tid + r * NT < LP) {
+                const uint32_t gi = qoff[r] + zo;
+                pre[r][0] = u[gi];
+                pre[r][1] = u[N + gi];
+                pre[r][2] = u[2u * N + gi];
+            }
     };
-    load_plane(0, z0 - 1);
-    load_plane(1, z0);
+    auto slot = [&](int zg) { return (zg - z0 + 4) & 3; };  // zg >= z0 - 1
+    auto store = [&](int zg) {
+        const int s = slot(zg);
+#pragma unroll
+        for (int r = 0; r < PQ; ++r)
+            if (tid + r * NT < LP) {
+                su[s][0][tid + r * NT] = pre[r][0];
+                su[s][1][tid + r * NT] = pre[r][1];
+                su[s][2][tid + r * NT] = pre[r][2];
+            }
+    };
+    fetch(z0 - 1);
+    store(z0 - 1);
+    fetch(z0);
+    store(z0);
+    fetch(z0 + 1);
     for (int z = z0; z < z1; ++z) {
-        const int k = z - z0;  // slots: z-1 -> k % 3, z -> (k+1) % 3, z+1 -> (k+2) % 3
-        load_plane((k + 2) % 3, z + 1);
+        store(z + 1);
+        if (z + 1 < z1) fetch(z + 2);
         __syncthreads();
         if (inxy) {
             const uint32_t n = (uint32_t)x + (uint32_t)y * (uint32_t)g.nx + (uint32_t)z * g.nxny;
             const uint32_t m = nbr[n];
             if (!(m & 1u)) {
-                const int sl[3] = {k % 3, (k + 1) % 3, (k + 2) % 3};
+                const int sl[3] = {slot(z - 1), slot(z), slot(z + 1)};
                 const int qc = (lx + 1) + LX * (ly + 1);
                 const float cx0 = su[sl[1]][0][qc], cy0 = su[sl[1]][1][qc], cz0 = su[sl[1]][2][qc];
                 float sx[27], sy[27], sz[27];
@@ -168,7 +196,6 @@ __device__ __forceinline__ void r1_rebuild_tile(const Grid &g, const PhaseTiling
                 r1_rebuild(N, n, sx, sy, sz, rec, fout);
             }
         }
-        __syncthreads();
     }
 }
 
