@@ -10,6 +10,7 @@ Eq. (15), and pulls them.  Checked here:
   and u within 1e-4 of max |u| (the plain step's bar); the same on ragged tiles,
   at density ratio 1000 with an initial velocity field, and at the full
   256 x 256 x 128 size in the benchmark's launch;
+* the 512^3 lattice (indices past 2^31): two launches agree, finite, volume kept;
 * the populations the rebuild kernel writes against the oracle's post-collision
   populations of the previous step (1e-5 of their maximum);
 * bitwise: repeated runs, graph replay against eager launches, save / load /
@@ -143,6 +144,39 @@ def test_r1_full_size_spreading(orc):
     w = W.spreading_256(0)
     print(f"[r1] full size {w.name} N={w.N}", flush=True)
     _cmp(gpu_run(w, 3, launch=tuning.launch_for(w.shape)), oracle_run(orc, w, 3), w, orc, 2e-6, 1e-5)
+
+
+def test_r1_512_cubed_lattice():
+    """The paper's 512^3 spreading lattice with collision = 1 (27 N above 2^31:
+    the rebuilt populations use the full unsigned 32-bit index range): two
+    steps (the first pulls each node's own equilibrium, the second the rebuilt
+    populations) in the benchmark's launch and in row-wide 512 x 1 tiles agree
+    on every node, stay finite and keep the phase-field volume."""
+    from paper_2607_25444_amd import capi, tuning
+    w = W.spreading_512()
+    assert 27 * w.N > 2 ** 31
+    fl = w.solid == 0
+    M0 = float(w.phi0.astype(np.float64)[fl].sum())
+    out = []
+    for launch in (tuning.launch_for(w.shape), (512, 1, 1, 0, 0)):
+        print(f"[r1 512^3] launch {launch}", flush=True)
+        s = capi.Sim(w.shape, _params(w))
+        s.set_launch(*launch)
+        s.set_geometry(w.solid, w.theta)
+        s.set_state(w.phi0)
+        s.step(2)
+        phi, u, _ = s.fields()
+        vol = s.volume()
+        s.sync()
+        out.append((phi.cpu().numpy(), u.cpu().numpy(), vol))
+        s.close()
+        del phi, u
+    (pa, ua, va), (pb, ub, vb) = out
+    assert np.isfinite(pa).all() and np.isfinite(ua).all()
+    assert np.abs(ua).max() > 0.0
+    assert np.abs(pa - pb)[fl].max() <= 2e-6
+    assert np.abs(ua - ub).max() <= 2e-5 * np.abs(ua).max()
+    assert va == pytest.approx(M0, rel=2e-7) and vb == pytest.approx(M0, rel=2e-7)
 
 
 @pytest.mark.parametrize("steps", [2, 6])
