@@ -516,9 +516,10 @@ __host__ __device__ __forceinline__ int wrapc(int v, int n)
 }
 
 // Element at a byte offset from a base pointer.  In the phase kernel the base
-// is a plane (uniform across the workgroup, held in scalar registers) and the
-// offset a 32-bit per-thread constant, so each access is one load or store
-// with a scalar base and no 64-bit address arithmetic.
+// is a plane (uniform across the workgroup) and the offset a 32-bit per-thread
+// constant: the per-thread part is computed once, not per plane.  (The
+// compiler still forms a 64-bit address for each access, one VALU instruction
+// per load; buffer loads without it were measured no faster here.)
 template <class T>
 __device__ __forceinline__ T &at_byte(T *base, uint32_t off)
 {
