@@ -9,7 +9,8 @@
 //   f[i*N + n]   post-collision populations of the previous step (pull layout)
 //   phi[n]       A/B buffers; fluid values and ghosts share the array
 //   u[d*N + n]   velocity of the last collision, read by the CAC advection
-//   a[d*N + n]   compressive flux phi(1-phi) n, written by H (fluid) and W (wall)
+//   a[d*N + n]   compressive flux phi(1-phi) n at wall nodes, written by W and read
+//                there by P (which forms the fluid values from its own phi planes)
 //   nbr[n]       bit 0: node is solid; bit i: node + c_i is solid
 //
 // Every kernel bounds-checks its node against the grid; bulk kernels map
