@@ -107,12 +107,13 @@ __device__ __forceinline__ void r1_stream_node(const Grid &g, const DevParams &p
 // the velocity planes z-1, z, z+1 (with a one-node halo in x and y) sit in a
 // ring of four LDS slots, so each velocity value is loaded from memory about
 // (CX+2)(CY+2)/(CX CY) times per chunk instead of 27 times.  Plane z+2 is
-// fetched into registers while plane z is rebuilt and enters the ring at the
-// start of the next plane, one barrier per plane: the slot it overwrites held
-// plane z-2, which no wave still reads once every wave has passed the barrier
-// of plane z-1 -- a wave can only get here after that.  Every thread takes part
-// in the loads and the barriers; threads outside the grid skip only the node
-// update.
+// fetched into registers while plane z is rebuilt and is written into the ring
+// at the start of plane z+1, into the slot of plane z-2.  The last reads of
+// that slot belong to the rebuild of plane z-1, which every wave finishes
+// before it arrives at the barrier of plane z; a wave starting plane z+1 has
+// passed that barrier, so one barrier per plane suffices.  Every thread takes
+// part in the loads and the barriers; threads outside the grid skip only the
+// node update.
 template <int CX, int CY>
 __device__ __forceinline__ void r1_rebuild_tile(const Grid &g, const PhaseTiling &pt, uint32_t tile,
                                                 const float *__restrict__ rec, const float *__restrict__ u,
