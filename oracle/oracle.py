@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 import subprocess
+from contextlib import contextmanager
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -74,41 +75,74 @@ class Params:
 _lib = None
 
 
+def build_variant(out_path: str, replacements) -> str:
+    """Compile a copy of the oracle with textual replacements (old, new) applied
+    to its C source into out_path.  For tests that plant a mistake in the oracle
+    and check that a pin catches it; every `old` must occur in the source."""
+    src = open(_SRC).read()
+    for old, new in replacements:
+        if old not in src:
+            raise ValueError(f"planted change not applicable: {old!r}")
+        src = src.replace(old, new)
+    csrc = out_path + ".c"
+    with open(csrc, "w") as f:
+        f.write(src)
+    subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-D_GNU_SOURCE",
+                    "-o", out_path, csrc, "-lm"], check=True)
+    return out_path
+
+
+@contextmanager
+def using_library(path: str):
+    """Route every call of this module to the oracle library at `path` (a
+    variant from build_variant) inside the block."""
+    global _lib
+    saved = _lib
+    _lib = _configure(C.CDLL(path))
+    try:
+        yield
+    finally:
+        _lib = saved
+
+
 def lib():
     global _lib
     if _lib is None:
-        path = build()
-        L = C.CDLL(path)
-        dp = C.POINTER(C.c_double)
-        u8p = C.POINTER(C.c_uint8)
-        i32p = C.POINTER(C.c_int32)
-        pp = C.POINTER(OrcParams)
-        L.orc_lattice.argtypes = [C.POINTER(C.c_int), dp, C.POINTER(C.c_int)]
-        L.orc_feq.argtypes = [C.c_double, dp, dp]
-        L.orc_guo.argtypes = [dp, dp, dp]
-        L.orc_fneq_reg.argtypes = [dp, dp, dp]
-        L.orc_collide_node.argtypes = [pp, C.c_double, dp, C.c_double, dp, dp, dp, dp]
-        L.orc_macro_node.argtypes = [pp, C.c_double, dp, C.c_double, dp, dp, dp, dp, dp]
-        L.orc_a2_local.argtypes = [C.c_double, dp, dp, dp, dp]
-        L.orc_post_node.argtypes = [C.c_double, dp, dp, C.c_double, dp, dp]
-        L.orc_a2grad.argtypes = [C.c_int, C.c_int, C.c_int, u8p, dp, dp, dp]
-        L.orc_grad_iso.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp]
-        L.orc_lap_iso.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp]
-        L.orc_wall_nodes.argtypes = [C.c_int, C.c_int, C.c_int, u8p, i32p, i32p, i32p, C.c_int]
-        L.orc_wall_nodes.restype = C.c_int
-        L.orc_ghost.argtypes = [pp, C.c_int, C.c_int, C.c_int, u8p, dp, dp, dp, dp]
-        L.orc_ghost.restype = C.c_int
-        L.orc_hydro.argtypes = [pp, C.c_int, C.c_int, C.c_int, u8p, dp, dp, dp, dp, dp, dp]
-        L.orc_phase.argtypes = [pp, C.c_int, C.c_int, C.c_int, u8p, dp, dp, dp, dp]
-        L.orc_volume.argtypes = [pp, C.c_int, C.c_int, C.c_int, u8p, dp, C.c_double, dp, dp]
-        L.orc_mass.argtypes = [C.c_int, C.c_int, C.c_int, u8p, dp]
-        L.orc_mass.restype = C.c_double
-        L.orc_init.argtypes = [C.c_int, C.c_int, C.c_int, u8p, dp, dp, dp, dp, dp, dp]
-        L.orc_step.argtypes = [pp, C.c_int, C.c_int, C.c_int, u8p, dp, dp, dp, dp, dp, C.c_double, C.c_int, dp]
-        L.orc_step.restype = C.c_int
-        L.orc_num_threads.restype = C.c_int
-        _lib = L
+        _lib = _configure(C.CDLL(build()))
     return _lib
+
+
+def _configure(L):
+    """Argument and result types of the oracle's exported functions."""
+    dp = C.POINTER(C.c_double)
+    u8p = C.POINTER(C.c_uint8)
+    i32p = C.POINTER(C.c_int32)
+    pp = C.POINTER(OrcParams)
+    L.orc_lattice.argtypes = [C.POINTER(C.c_int), dp, C.POINTER(C.c_int)]
+    L.orc_feq.argtypes = [C.c_double, dp, dp]
+    L.orc_guo.argtypes = [dp, dp, dp]
+    L.orc_fneq_reg.argtypes = [dp, dp, dp]
+    L.orc_collide_node.argtypes = [pp, C.c_double, dp, C.c_double, dp, dp, dp, dp]
+    L.orc_macro_node.argtypes = [pp, C.c_double, dp, C.c_double, dp, dp, dp, dp, dp]
+    L.orc_a2_local.argtypes = [C.c_double, dp, dp, dp, dp]
+    L.orc_post_node.argtypes = [C.c_double, dp, dp, C.c_double, dp, dp]
+    L.orc_a2grad.argtypes = [C.c_int, C.c_int, C.c_int, u8p, dp, dp, dp]
+    L.orc_grad_iso.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp]
+    L.orc_lap_iso.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp]
+    L.orc_wall_nodes.argtypes = [C.c_int, C.c_int, C.c_int, u8p, i32p, i32p, i32p, C.c_int]
+    L.orc_wall_nodes.restype = C.c_int
+    L.orc_ghost.argtypes = [pp, C.c_int, C.c_int, C.c_int, u8p, dp, dp, dp, dp]
+    L.orc_ghost.restype = C.c_int
+    L.orc_hydro.argtypes = [pp, C.c_int, C.c_int, C.c_int, u8p, dp, dp, dp, dp, dp, dp]
+    L.orc_phase.argtypes = [pp, C.c_int, C.c_int, C.c_int, u8p, dp, dp, dp, dp]
+    L.orc_volume.argtypes = [pp, C.c_int, C.c_int, C.c_int, u8p, dp, C.c_double, dp, dp]
+    L.orc_mass.argtypes = [C.c_int, C.c_int, C.c_int, u8p, dp]
+    L.orc_mass.restype = C.c_double
+    L.orc_init.argtypes = [C.c_int, C.c_int, C.c_int, u8p, dp, dp, dp, dp, dp, dp]
+    L.orc_step.argtypes = [pp, C.c_int, C.c_int, C.c_int, u8p, dp, dp, dp, dp, dp, C.c_double, C.c_int, dp]
+    L.orc_step.restype = C.c_int
+    L.orc_num_threads.restype = C.c_int
+    return L
 
 
 def _d(a):
