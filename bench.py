@@ -262,6 +262,90 @@ def bench_adjoint(torch, capi, tuning, W, steps, K, seed):
     return out
 
 
+def angle_study(args):
+    """Static contact-angle test of Sec. III A on the GPU path: a droplet of
+    radius R0 whose centre sits cz above the bottom solid layer (a cap at about
+    90 degrees) relaxes on a flat wall (rho = 1, nu = 0.04, sigma = 0.02) until
+    the fitted angle is stationary; the angle is measured by a sphere fit of
+    the phi = 1/2 surface and by the paper's circle fit in the central xz plane
+    (Eqs. (56)-(57)), both with the wall at z_w = 1/2.  Prints one JSON line per
+    measurement and one per run."""
+    import numpy as np
+    import torch
+    from paper_2607_25444_amd import capi
+    from paper_2607_25444_amd import tuning
+    from paper_2607_25444_amd import workloads as W
+    from tests import diagnostics as dg
+
+    shape = tuple(int(v) for v in args.angle_shape.split(","))
+    nx, ny, nz = shape
+    angles = [float(a) for a in args.angles.split(",")]
+    readings = [int(r) for r in args.wall_compression.split(",")]
+    solid = W.flat_walls(shape)
+    centre = ((nx - 1) / 2, (ny - 1) / 2, args.angle_cz)
+    phi0 = W.tanh_droplet(shape, centre, args.angle_R, args.delta).astype(np.float32)
+    launch = tuning.launch_for(shape)
+    rows = []
+    for wc in readings:
+        for th in angles:
+            prm = W.default_params(delta=args.delta, D=args.D, wall_compression=wc,
+                                   nu_l=args.nu, nu_g=args.nu, sigma=0.02)
+            sim = capi.Sim(shape, prm)
+            sim.set_launch(*launch)
+            sim.set_geometry(solid, W.uniform_theta(shape, th))
+            sim.set_state(phi0)
+            M0 = sim.volume()
+            t0 = time.perf_counter()
+            hist, steps, status = [], 0, "max_steps"
+            while steps < args.angle_steps:
+                sim.step(args.angle_every)
+                steps += args.angle_every
+                try:
+                    sim.sync()
+                except capi.CacError as e:
+                    status = f"non-finite after {steps} steps"
+                    break
+                phi, u, _ = sim.fields()
+                ph = phi.cpu().numpy().astype(np.float64)
+                umax = float(u.abs().max().item())
+                fluid = ph[solid == 0]
+                if fluid.max() < 0.5:
+                    status = "no liquid left"
+                    break
+                try:
+                    a_sph, c, Rf = dg.contact_angle_sphere(ph, shape)
+                    a_sec = dg.contact_angle_section(ph, shape, ny // 2)
+                except Exception:  # no interface near the wall any more (detached drop)
+                    status = f"fit failed after {steps} steps"
+                    break
+                zlow = dg.liquid_floor(ph, shape)
+                hist.append(a_sph)
+                print(json.dumps({"angle_study": "progress", "wall_compression": wc, "theta_imposed": th,
+                                  "steps": steps, "theta_sphere": round(a_sph, 3), "theta_section": round(a_sec, 3),
+                                  "fit_R": round(float(Rf), 3), "fit_z0": round(float(c[2]), 3),
+                                  "liquid_floor_z": zlow, "umax": umax}), flush=True)
+                if zlow > 1:
+                    status = f"detached after {steps} steps"
+                    break
+                if (steps >= args.angle_min_steps and len(hist) >= 3 and
+                        max(hist[-3:]) - min(hist[-3:]) < args.angle_tol):
+                    status = "stationary"
+                    break
+            M1 = sim.volume() if status != "non-finite" and not status.startswith("non-finite") else float("nan")
+            row = {"angle_study": "result", "shape": list(shape), "R0": args.angle_R, "cz": args.angle_cz,
+                   "delta": args.delta, "D": args.D, "nu": args.nu, "wall_compression": wc, "theta_imposed": th,
+                   "theta_sphere": round(hist[-1], 3) if hist else None,
+                   "theta_section": round(a_sec, 3) if hist else None,
+                   "steps": steps, "status": status, "volume_rel_drift": (M1 - M0) / M0,
+                   "wall_s": round(time.perf_counter() - t0, 1)}
+            rows.append(row)
+            print(json.dumps(row), flush=True)
+            sim.close()
+            del sim
+            torch.cuda.empty_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,6 +365,20 @@ def main():
     ap.add_argument("--no-r1", action="store_true", help="skip the gradient-form collision (collision = 1)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 1 GiB device copy (HBM ceiling; counter calibration)")
+    ap.add_argument("--angle-study", action="store_true",
+                    help="static contact-angle test of Sec. III A instead of the throughput benchmark")
+    ap.add_argument("--angle-shape", default="256,256,256")
+    ap.add_argument("--angle-R", type=float, default=40.0)
+    ap.add_argument("--angle-cz", type=float, default=2.0, help="droplet centre height (node units)")
+    ap.add_argument("--angles", default="30,60,90,120,150,160")
+    ap.add_argument("--wall-compression", default="1", help="comma list of readings of the wall flux")
+    ap.add_argument("--delta", type=float, default=4.0)
+    ap.add_argument("--D", type=float, default=0.1)
+    ap.add_argument("--nu", type=float, default=0.04)
+    ap.add_argument("--angle-steps", type=int, default=60000)
+    ap.add_argument("--angle-min-steps", type=int, default=20000)
+    ap.add_argument("--angle-every", type=int, default=4000)
+    ap.add_argument("--angle-tol", type=float, default=0.1)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -295,6 +393,9 @@ def main():
 
     if args.copy_probe:
         copy_probe(torch)
+        return
+    if args.angle_study:
+        angle_study(args)
         return
 
     if args.workload == "spreading":

@@ -78,3 +78,15 @@ def wetted_radius(phi, shape, z_layer=1):
     """r = sqrt(sum of phi over the first fluid layer / pi)."""
     nx, ny, nz = shape
     return float(np.sqrt(np.asarray(phi).reshape(nz, ny, nx)[z_layer].sum() / np.pi))
+
+
+def liquid_floor(phi, shape, level=0.5):
+    """Lowest fluid layer z >= 1 that holds a node with phi > level on the
+    central column region, or nz when there is none (a drop that left the
+    bottom wall has floor > 1)."""
+    nx, ny, nz = shape
+    phi3 = np.asarray(phi).reshape(nz, ny, nx)
+    for z in range(1, nz // 2):
+        if (phi3[z] > level).any():
+            return int(z)
+    return int(nz)
