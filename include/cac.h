@@ -349,9 +349,34 @@ cac_status cac_batch_profile(cac_batch *b, int nsteps, double *ms);
 cac_status cac_batch_destroy(cac_batch *b);
 cac_status cac_batch_last_error(cac_batch *b, char *buf, size_t n);
 
+/* ------------------------------------------------------------------------
+ * Allocation-free volume, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Handle-free variant of cac_volume: the phase-field volume
+ * M = sum over fluid nodes of phi (Eq. (48)), accumulated in FP64 by the same
+ * kernels and in the same order as cac_volume (equal inputs give bitwise
+ * equal results).
+ *   d_solid: device, N bytes, 1 = solid (only fluid nodes are summed);
+ *   d_phi:   device, N floats;
+ *   d_out:   device, 1 double, written stream-ordered (no synchronisation);
+ *   hip_stream: hipStream_t to launch on (NULL: the null stream).
+ * N = nx * ny * nz must not exceed 134217728 (= 2^27, e.g. 512^3): the block
+ * partials live in a static device array of 2^19 16-byte entries (8 MiB),
+ * which every GPU the library runs on holds until the process ends.  No
+ * memory is allocated or freed and no memset is issued; every partial is
+ * written before it is read.  All calls on one device share that device's
+ * array: calls that overlap in time on one device (two streams, two host
+ * threads) race and must be serialised by the caller.
+ * Errors: CAC_ERR_ARG (empty axis, N above the limit, null pointer; the text
+ * is kept for cac_last_error(NULL, ...)), CAC_ERR_HIP (launch failure). */
+cac_status cac_volume_noalloc(int nx, int ny, int nz, const uint8_t *d_solid, const float *d_phi, double *d_out,
+                              void *hip_stream);
+
 const char *cac_status_string(cac_status s);
 
-/* Copy the message of the last failed call on h into buf (n bytes). */
+/* Copy the message of the last failed call on h into buf (n bytes); with
+ * h = NULL, the message of the last failed handle-free call of the calling
+ * thread (cac_volume_noalloc). */
 cac_status cac_last_error(cac_handle *h, char *buf, size_t n);
 
 #ifdef __cplusplus

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcac.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["kernels.hip", "r1.hip", "batch.hip", "adjoint.hip", "probe.hip", "runtime.cpp", "batch_runtime.cpp", "adjoint_runtime.cpp"]
+SOURCES = ["kernels.hip", "r1.hip", "batch.hip", "adjoint.hip", "probe.hip", "noalloc.hip", "runtime.cpp", "batch_runtime.cpp", "adjoint_runtime.cpp"]
 
 # Packed FP32 instructions are disabled on purpose (the compiler would form
 # them from float2-like code); every other flag is ordinary optimisation.

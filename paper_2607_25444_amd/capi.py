@@ -84,6 +84,7 @@ SIGNATURES = {
     "cac_batch_profile": (C.c_int, [_hp, C.c_int, C.POINTER(C.c_double)]),
     "cac_batch_destroy": (C.c_int, [_hp]),
     "cac_batch_last_error": (C.c_int, [_hp, C.c_char_p, C.c_size_t]),
+    "cac_volume_noalloc": (C.c_int, [C.c_int, C.c_int, C.c_int, _vp, _vp, _vp, _vp]),
     "cac_status_string": (C.c_char_p, [C.c_int]),
     "cac_last_error": (C.c_int, [_hp, C.c_char_p, C.c_size_t]),
 }
@@ -142,6 +143,22 @@ def wall_tables(solid, shape):
 
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def volume_noalloc(shape, d_solid, d_phi, d_out, stream=None):
+    """cac_volume_noalloc: FP64 fluid sum of d_phi (torch uint8 mask, float32
+    field, float64 output of one element, all on the current device), launched
+    on `stream` (a torch stream; None: torch's current stream).  Asynchronous."""
+    lib = load_library()
+    nx, ny, nz = shape
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    st = lib.cac_volume_noalloc(nx, ny, nz, _ptr(d_solid), _ptr(d_phi), _ptr(d_out), C.c_void_p(stream.cuda_stream))
+    if st != CAC_OK:
+        buf = C.create_string_buffer(512)
+        lib.cac_last_error(None, buf, 512)
+        raise CacError(st, buf.value.decode())
 
 
 class Sim:

@@ -168,6 +168,11 @@ hipError_t launch_init(const Grid &g, const Fields &F, int fcur, const float *u0
                        hipStream_t s);
 hipError_t launch_mass(const Grid &g, const Tiling &t, const Fields &F, const float *phi, double *out,
                        hipStream_t s);
+// The same FP64 fluid sum of phi with the block partials in `partial`
+// (mass_partials(N) entries, all written before they are read); out: device.
+uint32_t mass_partials(uint32_t N);
+hipError_t launch_mass_into(uint32_t N, const uint8_t *solid, const float *phi, double2 *partial, double *out,
+                            hipStream_t s);
 // p* on fluid nodes after a step: the sum of the first `npl` planes of
 // F.f[fcur] (27: the post-collision populations; 1: the record of the
 // gradient-form path).

@@ -396,15 +396,25 @@ hipError_t launch_init(const Grid &g, const Fields &F, int fcur, const float *u0
     return hipGetLastError();
 }
 
+uint32_t mass_partials(uint32_t N) { return (uint32_t)blocks_for(N, 256); }
+
+hipError_t launch_mass_into(uint32_t N, const uint8_t *solid, const float *phi, double2 *partial, double *out,
+                            hipStream_t s)
+{
+    // `partial` holds mass_partials(N) entries; every one is written before it is read
+    const unsigned nb = mass_partials(N);
+    k_mass_partial<<<nb, 256, 0, s>>>(N, solid, phi, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_mass_final<<<1, 1024, 0, s>>>(partial, nb, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_mass(const Grid &g, const Tiling &t, const Fields &F, const float *phi, double *out, hipStream_t s)
 {
     // the partial array holds at least one entry per 256 nodes (sized by the runtime)
-    const unsigned nb = blocks_for(g.N, 256);
-    k_mass_partial<<<nb, 256, 0, s>>>(g.N, F.solid, phi, F.partial);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_mass_final<<<1, 1024, 0, s>>>(F.partial, nb, out);
-    return hipGetLastError();
+    (void)t;
+    return launch_mass_into(g.N, F.solid, phi, F.partial, out, s);
 }
 
 hipError_t launch_gather(const Grid &g, const Fields &F, int fcur, int pcur, int stepped, int npl, float *phi_out,

@@ -22,6 +22,7 @@ Tiling make_tiling(const Grid &g, int bx, int by, int bz);
 void build_geometry(const Grid &g, const uint8_t *solid, std::vector<uint32_t> &nbr, std::vector<int32_t> &widx,
                     std::vector<int32_t> &wn6, std::vector<int32_t> &wdonor, int &nskip);
 bool valid_params(const cac_params &p);
+const char *free_call_error();  // last failed handle-free call of this thread (noalloc.hip)
 }  // namespace cac
 
 namespace cac {
@@ -266,8 +267,8 @@ const char *cac_status_string(cac_status s)
 
 cac_status cac_last_error(cac_handle *h, char *buf, size_t n)
 {
-    if (!h || !buf || n == 0) return CAC_ERR_ARG;
-    snprintf(buf, n, "%s", h->err.c_str());
+    if (!buf || n == 0) return CAC_ERR_ARG;
+    snprintf(buf, n, "%s", h ? h->err.c_str() : free_call_error());
     return CAC_OK;
 }
 
