@@ -81,11 +81,17 @@ typedef struct {
                                      stored between steps).  With 1, cac_get_populations and the
                                      adjoint (cac_tape_*, cac_adjoint) are refused with
                                      CAC_ERR_STATE; a batch takes it when all its domains do. */
+    int ghost_localization;  /* factor lambda_s of the ghost extrapolation, Eq. (46):
+                                1 -> sqrt(4 phi_f (1 - phi_f)) of Eq. (47) (the paper's; default);
+                                0 -> 1 (a diagnostic reading for the contact-angle study: the
+                                     ghost is the plain first-order extrapolation).  The adjoint
+                                     (cac_tape_*, cac_adjoint) is refused with CAC_ERR_STATE for 0. */
 } cac_params;
 
 /* Fill p with the defaults (rho = 1, nu = 0.04, sigma = 0.02, delta = 4,
  * D = 0.1, g = 0, eps_phi = 1e-3, eps_n = 1e-12, sin_tol = 1e-6,
- * cot_max = 1e6, volume_correction = 1, wall_compression = 1, collision = 0). */
+ * cot_max = 1e6, volume_correction = 1, wall_compression = 1, collision = 0,
+ * ghost_localization = 1). */
 cac_status cac_default_params(cac_params *p);
 
 /* Create a handle for an nx * ny * nz lattice on the current HIP device.

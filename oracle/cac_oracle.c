@@ -58,6 +58,8 @@ typedef struct {
     int collision;                   /* non-equilibrium moment A2 of Eq. (14): 0 -> local second
                                       * moment of the pre-collision populations; 1 -> gradient
                                       * form of Eq. (15) from the velocity field */
+    int ghost_localization;          /* factor of the ghost extrapolation, Eq. (46): 1 -> lambda_s of
+                                      * Eq. (47); 0 -> 1 (diagnostic reading of the angle study) */
 } orc_params;
 
 /* ------------------------------------------------------------------ */
@@ -427,7 +429,36 @@ int orc_wall_nodes(int nx, int ny, int nz, const uint8_t *solid, int32_t *idx, i
 }
 
 /* ------------------------------------------------------------------ */
-/* Substep W: ghost-node wetting update (Sec. II B and its pseudo-code)  */
+/* Substep W: ghost-node wetting update (Sec. II B, Eqs. (36)-(47))      */
+
+/* Ghost value of a wall node with donor link q (x_f = x_s + c_q), unit wall
+ * normal n_w (Eq. (38), pointing into the solid), donor value phi_f and
+ * isotropic donor gradient G (Eq. (22)).  With G_par = G - (G.n_w) n_w the
+ * tangential gradient (Eq. (42)), theta_c = pi - theta (Eq. (43)), the
+ * corrected gradient G_c = G_par + d_n n_w with d_n = -|G_par| cot(theta_c)
+ * (Eqs. (44)-(45)) and r_fs = -c_q (Eq. (41)), the extrapolation of Eq. (46)
+ * is, in closed form,
+ *   phi_g = phi_f + lambda_s G_c . r_fs
+ *         = phi_f - lambda_s [ c_q . G_par - |G_par| cot(theta_c) (c_q . n_w) ],
+ * lambda_s from Eq. (47) (or 1 for the diagnostic reading).  Gc receives the
+ * corrected gradient (it sets the compressive flux on the wall node). */
+static double ghost_value(const orc_params *p, int q, const double nw[3], double phi_f, const double G[3],
+                          double theta, double Gc[3])
+{
+    const double gn = G[0] * nw[0] + G[1] * nw[1] + G[2] * nw[2];
+    double Gpar[3];
+    for (int d = 0; d < 3; ++d) Gpar[d] = G[d] - gn * nw[d];
+    const double t = sqrt(Gpar[0] * Gpar[0] + Gpar[1] * Gpar[1] + Gpar[2] * Gpar[2]);
+    /* cot(theta_c), replaced by +-cot_max where |sin(theta_c)| < sin_tol (text after Eq. (45)) */
+    const double sc = sin(M_PI - theta), cc = cos(M_PI - theta);
+    const double cot_c = (fabs(sc) < p->sin_tol) ? copysign(p->cot_max, cc) : cc / sc;
+    for (int d = 0; d < 3; ++d) Gc[d] = Gpar[d] - t * cot_c * nw[d];
+    const double cq_par = CV[q][0] * Gpar[0] + CV[q][1] * Gpar[1] + CV[q][2] * Gpar[2];
+    const double cq_n = CV[q][0] * nw[0] + CV[q][1] * nw[1] + CV[q][2] * nw[2];
+    const double l2 = 4.0 * phi_f * (1.0 - phi_f);
+    const double lambda_s = p->ghost_localization ? sqrt(l2 > 0.0 ? l2 : 0.0) : 1.0;
+    return phi_f - lambda_s * (cq_par - t * cot_c * cq_n);
+}
 
 /* phi_in: phi^n on fluid nodes and the previous ghosts on wall nodes.
  * theta: prescribed contact angle (radians) per node, read at wall nodes.
@@ -460,30 +491,12 @@ int orc_ghost(const orc_params *p, int nx, int ny, int nz, const uint8_t *solid,
         double nn = sqrt((double)n6[3 * k] * n6[3 * k] + (double)n6[3 * k + 1] * n6[3 * k + 1] +
                          (double)n6[3 * k + 2] * n6[3 * k + 2]);
         double nw[3] = {n6[3 * k] / nn, n6[3 * k + 1] / nn, n6[3 * k + 2] / nn};
-        /* donor node and donor-to-solid displacement, Eq. (41) */
+        /* donor node x_f = x_s + c_q (Eq. (41)), its value and isotropic gradient */
         const long xf = neighbour(&g, xs, q);
-        const double r_fs[3] = {-CV[q][0], -CV[q][1], -CV[q][2]};
         const double phi_f = phi_in[xf];
-        double Gf[3];
+        double Gf[3], Gc[3];
         grad_iso_at(&g, phi_in, xf, Gf);
-        /* tangential gradient, Eq. (42) */
-        double gn = Gf[0] * nw[0] + Gf[1] * nw[1] + Gf[2] * nw[2];
-        double Gpar[3];
-        for (int d = 0; d < 3; ++d) Gpar[d] = Gf[d] - gn * nw[d];
-        double t = sqrt(Gpar[0] * Gpar[0] + Gpar[1] * Gpar[1] + Gpar[2] * Gpar[2]);
-        /* internal angle Eq. (43) and regularised cotangent */
-        double theta_c = M_PI - theta[xs];
-        double sc = sin(theta_c), cc = cos(theta_c);
-        double cot = (fabs(sc) < p->sin_tol) ? copysign(p->cot_max, cc) : cc / sc;
-        /* normal derivative Eq. (44) and corrected gradient Eq. (45) */
-        double dn = -t * cot;
-        double Gc[3];
-        for (int d = 0; d < 3; ++d) Gc[d] = Gpar[d] + dn * nw[d];
-        /* localisation factor Eq. (47), clipped at 0 below */
-        double lam2 = 4.0 * phi_f * (1.0 - phi_f);
-        double lam = sqrt(lam2 > 0.0 ? lam2 : 0.0);
-        /* extrapolation Eq. (46) */
-        const double gv = phi_f + lam * (Gc[0] * r_fs[0] + Gc[1] * r_fs[1] + Gc[2] * r_fs[2]);
+        const double gv = ghost_value(p, q, nw, phi_f, Gf, theta[xs], Gc);
         phi_hat[xs] = gv;
         if (a_wall && p->wall_compression) {
             double gc2 = Gc[0] * Gc[0] + Gc[1] * Gc[1] + Gc[2] * Gc[2];
@@ -731,6 +744,9 @@ int orc_volume(const orc_params *p, int nx, int ny, int nz, const uint8_t *solid
 
 /* Threads the OpenMP loops use. */
 int orc_num_threads(void) { return omp_get_max_threads(); }
+
+/* Set the number of threads of the OpenMP loops (n >= 1). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 
 /* Phase-field mass, Eq. (48): sum of phi over fluid nodes. */
 double orc_mass(int nx, int ny, int nz, const uint8_t *solid, const double *phi)

@@ -31,7 +31,8 @@ class CacParams(C.Structure):
     _fields_ = [("rho_l", C.c_double), ("rho_g", C.c_double), ("nu_l", C.c_double), ("nu_g", C.c_double),
                 ("sigma", C.c_double), ("delta", C.c_double), ("D", C.c_double), ("g", C.c_double * 3),
                 ("eps_phi", C.c_double), ("eps_n", C.c_double), ("sin_tol", C.c_double), ("cot_max", C.c_double),
-                ("volume_correction", C.c_int), ("wall_compression", C.c_int), ("collision", C.c_int)]
+                ("volume_correction", C.c_int), ("wall_compression", C.c_int), ("collision", C.c_int),
+                ("ghost_localization", C.c_int)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)

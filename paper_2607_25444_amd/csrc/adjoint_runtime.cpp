@@ -263,6 +263,8 @@ cac_status cac_tape_forward(cac_handle *h, int nsteps, int K)
     if (nsteps < 1 || K < 1) return fail(h, CAC_ERR_ARG, "nsteps and K must be >= 1");
     if (!h->state) return fail(h, CAC_ERR_STATE, "cac_set_state must come first");
     if (h->prm.collision != 0) return fail(h, CAC_ERR_STATE, "the adjoint is built for collision = 0");
+    if (h->prm.ghost_localization != 1)
+        return fail(h, CAC_ERR_STATE, "the adjoint is built for the localisation factor of Eq. (47)");
     AdjTape &T = *tape_of(h);
     T.recorded = false;
     const size_t N = h->g.N;

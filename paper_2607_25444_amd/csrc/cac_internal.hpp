@@ -57,6 +57,7 @@ struct DevParams {
     float sin_tol, cot_max;
     int volume_correction;
     int wall_compression;
+    int ghost_lambda;        // 1: lambda_s of Eq. (47) in the ghost extrapolation; 0: lambda_s = 1
     int variable_density;    // drho != 0: pressure and viscous corrections are live
     int rev_order;           // debug: W, H and P take their workgroups in reverse order
 };

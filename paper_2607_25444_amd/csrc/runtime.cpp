@@ -58,7 +58,8 @@ namespace cac {
 bool valid_params(const cac_params &p)
 {
     return p.rho_l > 0 && p.rho_g > 0 && p.nu_l > 0 && p.nu_g > 0 && p.delta > 0 && p.D >= 0 && p.sigma >= 0 &&
-           p.eps_phi >= 0 && p.eps_phi < 0.5 && (p.collision == 0 || p.collision == 1);
+           p.eps_phi >= 0 && p.eps_phi < 0.5 && (p.collision == 0 || p.collision == 1) &&
+           (p.ghost_localization == 0 || p.ghost_localization == 1);
 }
 
 DevParams make_dev_params(const cac_params &p)
@@ -81,6 +82,7 @@ DevParams make_dev_params(const cac_params &p)
     d.cot_max = (float)p.cot_max;
     d.volume_correction = p.volume_correction ? 1 : 0;
     d.wall_compression = p.wall_compression ? 1 : 0;
+    d.ghost_lambda = p.ghost_localization ? 1 : 0;
     d.variable_density = (p.rho_l != p.rho_g) ? 1 : 0;
     return d;
 }
@@ -288,6 +290,7 @@ cac_status cac_default_params(cac_params *p)
     p->volume_correction = 1;
     p->wall_compression = 1;
     p->collision = 0;
+    p->ghost_localization = 1;
     return CAC_OK;
 }
 

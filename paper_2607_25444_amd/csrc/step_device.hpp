@@ -144,13 +144,16 @@ __device__ __forceinline__ float feq_one(float ps, float ux, float uy, float uz)
 
 // ------------------------------------------------------------------ W: ghosts
 
-// One thread per wall node b (Sec. II B, the ghost-node update):
-//   donor x_f = b + c_q*, phi_f and the isotropic gradient at x_f (fluid
-//   stencil points from the current buffer, wall points from the previous
-//   ghosts in the other buffer: Jacobi), tangential gradient (Eq. (42)),
-//   theta_c = pi - theta (Eq. (43)), normal derivative (Eq. (44)), corrected
-//   gradient (Eq. (45)), lambda_s (Eq. (47)), ghost (Eq. (46)) written to the
-//   current buffer.  Reads only fluid data and old ghosts, writes only b.
+// Ghost value of wall node b (Sec. II B, Eqs. (36)-(47)), one thread per
+// wall node.  Donor x_f = b + c_q (Eq. (41)); phi_f and the isotropic
+// gradient G at x_f (Eq. (22)) from fluid values of the current buffer and,
+// at wall points of the stencil, the previous ghosts in the other buffer
+// (Jacobi).  With the unit wall normal n_w (Eq. (38)), the tangential gradient
+// G_par = G - (G.n_w) n_w (Eq. (42)) and theta_c = pi - theta (Eq. (43)), the
+// corrected gradient of Eqs. (44)-(45) is G_c = G_par - |G_par| cot(theta_c) n_w
+// and the extrapolation of Eq. (46) along r_fs = -c_q reads
+//   phi_g = phi_f - lambda_s [ c_q.G_par - |G_par| cot(theta_c) (c_q.n_w) ],
+// lambda_s of Eq. (47).  Reads only fluid data and old ghosts, writes only b.
 __device__ __forceinline__ void ghost_node(const Grid &g, const DevParams &p, int k, const int32_t *__restrict__ widx,
                                            const uint8_t *__restrict__ wq, const float *__restrict__ wn,
                                            const float *__restrict__ theta, float *phi_cur,
@@ -190,19 +193,22 @@ __device__ __forceinline__ void ghost_node(const Grid &g, const DevParams &p, in
     const float phif = s[13];
     const float nx = wn[3 * k], ny = wn[3 * k + 1], nz = wn[3 * k + 2];
     const float gn = gx * nx + gy * ny + gz * nz;
-    const float px = gx - gn * nx, py = gy - gn * ny, pz = gz - gn * nz;
+    const float px = gx - gn * nx, py = gy - gn * ny, pz = gz - gn * nz;  // G_par
     const float t = sqrtf(px * px + py * py + pz * pz);
     const float thc = 3.14159265358979f - theta[k];
     float sn, cs;
     sincosf(thc, &sn, &cs);
+    // cot(theta_c), replaced by +-cot_max where |sin(theta_c)| < sin_tol
     const float cot = (fabsf(sn) < p.sin_tol) ? copysignf(p.cot_max, cs) : cs / sn;
-    const float dn = -t * cot;
-    const float cgx = px + dn * nx, cgy = py + dn * ny, cgz = pz + dn * nz;
+    const float tc = t * cot;
+    const float cq_par = (float)cxq * px + (float)cyq * py + (float)czq * pz;
+    const float cq_n = (float)cxq * nx + (float)cyq * ny + (float)czq * nz;
     const float l2 = 4.0f * phif * (1.0f - phif);
-    const float lam = sqrtf(l2 > 0.0f ? l2 : 0.0f);
-    const float gv = phif - lam * (cgx * (float)cxq + cgy * (float)cyq + cgz * (float)czq);
+    const float lam = p.ghost_lambda ? sqrtf(l2 > 0.0f ? l2 : 0.0f) : 1.0f;
+    const float gv = phif - lam * (cq_par - tc * cq_n);
     phi_cur[b] = gv;
     if (p.wall_compression) {
+        const float cgx = px - tc * nx, cgy = py - tc * ny, cgz = pz - tc * nz;  // G_c
         const float c2 = cgx * cgx + cgy * cgy + cgz * cgz;
         float ax = 0.f, ay = 0.f, az = 0.f;
         if (c2 > p.eps_n2) {
@@ -453,22 +459,6 @@ __device__ __forceinline__ void hydro_node(const Grid &g, const DevParams &p, co
 
 // ------------------------------------------------------------------ P: CAC
 
-__device__ __forceinline__ float minmod(float a, float b)
-{
-    // Eq. (32)
-    return (a * b <= 0.0f) ? 0.0f : (a > 0.0f ? fminf(a, b) : fmaxf(a, b));
-}
-
-// Face flux between nodes L and R (R = L + e_d), Eqs. (30)-(34):
-// u_f = (u_L + u_R)/2, minmod slopes at L and R, upwind reconstruction.
-__device__ __forceinline__ float muscl_flux(float pLL, float pL, float pR, float pRR, float uL, float uR)
-{
-    const float uf = 0.5f * (uL + uR);
-    const float sL = minmod(pL - pLL, pR - pL);
-    const float sR = minmod(pR - pL, pRR - pR);
-    return uf * (uf >= 0.0f ? pL + 0.5f * sL : pR - 0.5f * sR);
-}
-
 template <int NT>
 __device__ __forceinline__ void block_sum2(double &x, double &y)
 {
@@ -557,10 +547,15 @@ __device__ __forceinline__ PlaneSums plane_sums(const float (&v)[9])
 }
 
 // minmod of Eq. (32) in branch-free form: equal to 0 when ab <= 0, else the
-// argument of smaller magnitude.
+// argument of smaller magnitude -- which is the median of a, b and 0 (one
+// v_med3_f32 on the device).
 __host__ __device__ __forceinline__ float minmod2(float a, float b)
 {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_fmed3f(a, b, 0.0f);
+#else
     return fmaxf(fminf(a, b), 0.0f) + fminf(fmaxf(a, b), 0.0f);
+#endif
 }
 
 // The two face fluxes of a node along one axis from phi at offsets -2..+2 and

@@ -45,7 +45,7 @@ class Workload:
 def default_params(**kw) -> dict:
     p = dict(rho_l=1.0, rho_g=1.0, nu_l=0.04, nu_g=0.04, sigma=0.02, delta=4.0, D=0.1,
              g=(0.0, 0.0, 0.0), eps_phi=1e-3, eps_n=1e-12, sin_tol=1e-6, cot_max=1e6,
-             volume_correction=1, wall_compression=1)
+             volume_correction=1, wall_compression=1, ghost_localization=1)
     p.update(kw)
     return p
 

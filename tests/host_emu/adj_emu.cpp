@@ -43,6 +43,7 @@ extern "C" int emu_reverse_step(int nx, int ny, int nz, const double *prm, const
     p.cot_max = (float)prm[13];
     p.volume_correction = prm[14] != 0;
     p.wall_compression = prm[15] != 0;
+    p.ghost_lambda = 1;
     p.variable_density = prm[0] != prm[1];
     std::vector<uint32_t> nbr(N);
     for (int z = 0; z < nz; ++z)
