@@ -1,19 +1,26 @@
 #!/usr/bin/env python3
 """Throughput of the coupled CAC lattice Boltzmann wetting step on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload spreading]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload orifice]
 
-Workload (N = 1): the short-time spreading droplet, 256 x 256 x 128 lattice,
-flat walls, sphere R = 40 touching the wall, interface width 4, FP32 state,
-seed 0 (synthetic input, see paper_2607_25444_amd/workloads.py).  Inputs are
-resident in HBM before the timed region; K steps are timed with HIP events
-on the stream the library launches on, bracketed by device synchronisation.
-Prints one JSON line:
+Workload (N = 1): the gravity-driven passage through a sharp-edged orifice,
+192 x 192 x 768 lattice (28.3 M nodes), plate 8 cells thick with a hole of
+diameter 48, droplet R = 40, density and viscosity contrast (1.2/0.9,
+0.031/0.24) and a body force, FP32 state, seed 0 (synthetic input, see
+paper_2607_25444_amd/workloads.py): the largest plain-step lattice and the
+one where every force term of the step is live.  Inputs are resident in HBM
+before the timed region; K steps are timed with HIP events on the stream the
+library launches on, bracketed by device synchronisation.  Prints one JSON
+line:
   value      fluid-node MLUPS of the plain step (whole job, one GPU)
   roofline   the dominant kernel (hydrodynamic collide-stream) against the
              HBM peak: algorithmic bytes (27 populations read and written +
-             phi read = 220 B per fluid node) / its average launch time,
-             timed live with per-kernel HIP events
+             phi read = 220 B per fluid node) x fluid nodes / its average launch
+             time, timed live with per-kernel HIP events; `step` gives the
+             whole step against the same peak (224 B per fluid node)
+  spreading  the same for the 256 x 256 x 128 spreading workload
+  r1, batched, adjoint   the gradient-form collision, the 64-domain batch and
+             the reverse-mode sweep, each beside the plain step
   cpu_baseline  the FP64 oracle timed on the host on a bounded sample
 """
 from __future__ import annotations
@@ -51,30 +58,122 @@ def kernel_source_hash():
 
 
 def measured_traffic(workload_name):
-    """HBM bytes per hydro launch from the committed rocprofv3 counter summary,
-    if it was taken on this workload and on the current kernel source; else None."""
-    p = os.path.join(ROOT, "profiles", "hydro_traffic_spreading_256x256x128.json")
-    if workload_name != "spreading_256x256x128" or not os.path.exists(p):
+    """HBM bytes per hydro launch from the committed rocprofv3 counter summary
+    for this workload, if there is one and it was taken on the current kernel
+    source; else None."""
+    p = os.path.join(ROOT, "profiles", f"hydro_traffic_{workload_name}.json")
+    if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+    if d.get("workload") != workload_name or d.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(w, steps):
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, steps, W):
+    """The FP64 oracle on the host: `steps` steps of the benchmark workload on
+    all threads, and one step of the 256x256x128 spreading workload on one
+    thread (a bounded sample each)."""
     import numpy as np
     import oracle
 
-    p = oracle.Params(**w.params)
-    s = oracle.OracleSim.create(w.shape, w.solid, w.theta.astype(np.float64), p, w.phi0.astype(np.float64))
-    t0 = time.perf_counter()
-    s.step(steps)
-    dt = time.perf_counter() - t0
-    return dict(value=round(w.n_fluid * steps / dt / 1e6, 4), unit="MLUPS", cores=oracle.num_threads(),
-                kind="oracle",
+    def timed(wl, n):
+        p = oracle.Params(**wl.params)
+        s = oracle.OracleSim.create(wl.shape, wl.solid, wl.theta.astype(np.float64), p, wl.phi0.astype(np.float64))
+        t0 = time.perf_counter()
+        s.step(n)
+        return time.perf_counter() - t0
+
+    threads = oracle.num_threads()
+    dt = timed(w, steps)
+    ws = W.spreading_256(0)
+    oracle.set_threads(1)
+    dt1 = timed(ws, 1)
+    oracle.set_threads(threads)
+    return dict(value=round(w.n_fluid * steps / dt / 1e6, 4), unit="MLUPS", cores=threads, kind="oracle",
                 sample=f"{steps} full steps of the {w.name} workload ({w.n_fluid} fluid nodes), FP64, "
-                       f"{dt:.1f} s wall")
+                       f"{dt:.1f} s wall on {threads} threads",
+                value_1core=round(ws.n_fluid / dt1 / 1e6, 4),
+                sample_1core=f"1 full step of the {ws.name} workload ({ws.n_fluid} fluid nodes) on 1 thread, "
+                             f"{dt1:.1f} s wall",
+                cpu_model=host_cpu_model(), nproc=os.cpu_count())
+
+
+def workload_of(W, name, seed):
+    return {"spreading": lambda: W.spreading_256(seed), "orifice": lambda: W.orifice_192(seed),
+            "porous": lambda: W.porous_256(seed), "impact": lambda: W.impact_256(),
+            "spreading512": lambda: W.spreading_512(), "sessile": lambda: W.sessile_32(60.0)}[name]()
+
+
+def plain_block(torch, capi, w, launch, steps, warmup, probes):
+    """Plain step on workload w: `steps` steps timed with HIP events on the
+    library's stream after `warmup` untimed ones, then per-kernel times (HIP
+    events around every kernel) and, with probes, the live bandwidth ceilings."""
+    sim = capi.Sim(w.shape, w.params)
+    sim.set_launch(*launch)
+    sim.set_geometry(w.solid, w.theta)
+    sim.set_state(w.phi0, w.meta.get("u0"))
+    M0 = sim.volume()
+    sim.step(warmup)
+    sim.sync()
+    stream = sim.stream
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    sim.step(steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    sim.sync()
+    ms_step = ms / max(steps, 1)
+    kp = min(steps, 100)
+    kavg = [v / kp for v in sim.profile_step(kp)]
+    M1 = sim.volume()
+    hydro_gbs = w.n_fluid * HYDRO_BYTES_PER_LU / (kavg[1] * 1e-3) / 1e9
+    step_gbs = w.n_fluid * STEP_BYTES_PER_LU / (ms_step * 1e-3) / 1e9
+    out = {
+        "workload": w.name, "fluid_nodes": w.n_fluid, "launch": list(launch), "steps": steps,
+        "ms_per_step": round(ms_step, 5), "value": round(w.n_fluid / (ms_step * 1e-3) / 1e6, 2), "unit": "MLUPS",
+        "kernel_ms": {"W": round(kavg[0], 5), "H": round(kavg[1], 5), "P": round(kavg[2], 5), "V": round(kavg[3], 5)},
+        "hydro_algorithmic_GBs": round(hydro_gbs, 1),
+        "wall_nodes": sim.nwall,
+        "step": {
+            "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+            "bytes_per_lu": STEP_BYTES_PER_LU,
+            "algorithmic_GBs": round(step_gbs, 1),
+            "frac_of_peak": round(step_gbs / HBM_PEAK_GBS, 4),
+            "kernel_ms": {"W": round(kavg[0], 5), "H": round(kavg[1], 5), "P": round(kavg[2], 5),
+                          "V": round(kavg[3], 5)},
+            "mlups_all_nodes": round(w.N / (ms_step * 1e-3) / 1e6, 2),
+            "volume_rel_drift": (M1 - M0) / M0,
+        },
+    }
+    if probes:
+        # achievable ceilings, measured live after the timed region: the
+        # collide-stream's memory access pattern without its arithmetic (27-plane
+        # pull copy, 216 B per node over all nodes; leaves the handle without a
+        # state) and a plain 1 GiB streaming copy
+        pull_ms = sim.pull_copy_probe(20)
+        pull_gbs = w.N * 216 / (pull_ms * 1e-3) / 1e9
+        copy_gbs = copy_probe(torch, reps=10, quiet=True)
+        out["ceilings"] = {"pull_copy_GBs": round(pull_gbs, 1), "pull_copy_ms": round(pull_ms, 5),
+                           "plain_copy_GBs": round(copy_gbs, 1),
+                           "hydro_algorithmic_over_pull_copy": round(hydro_gbs / pull_gbs, 4)}
+        log(f"[bench] ceilings: pull copy {pull_gbs:.0f} GB/s ({pull_ms:.4f} ms), plain copy {copy_gbs:.0f} GB/s")
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return out
 
 
 def copy_probe(torch, nbytes=1 << 30, reps=20, quiet=False):
@@ -280,16 +379,28 @@ def angle_study(args):
     shape = tuple(int(v) for v in args.angle_shape.split(","))
     nx, ny, nz = shape
     angles = [float(a) for a in args.angles.split(",")]
-    readings = [int(r) for r in args.wall_compression.split(",")]
+    readings = [(int(r), int(l)) for r in args.wall_compression.split(",")
+                for l in args.ghost_localization.split(",")]
     solid = W.flat_walls(shape)
     centre = ((nx - 1) / 2, (ny - 1) / 2, args.angle_cz)
-    phi0 = W.tanh_droplet(shape, centre, args.angle_R, args.delta).astype(np.float32)
+    phi_sphere = W.tanh_droplet(shape, centre, args.angle_R, args.delta).astype(np.float32)
+    vol0 = float(phi_sphere[solid == 0].astype(np.float64).sum())
     launch = tuning.launch_for(shape)
     rows = []
-    for wc in readings:
+    for wc, gl in readings:
         for th in angles:
-            prm = W.default_params(delta=args.delta, D=args.D, wall_compression=wc,
+            prm = W.default_params(delta=args.delta, D=args.D, wall_compression=wc, ghost_localization=gl,
                                    nu_l=args.nu, nu_g=args.nu, sigma=0.02)
+            if args.angle_init == "cap":
+                # spherical cap meeting the wall (z_w = 1/2) at the imposed angle, with the
+                # liquid volume of the paper's initial droplet
+                ct = np.cos(np.deg2rad(th))
+                Rc = (3.0 * vol0 / (np.pi * (2.0 - 3.0 * ct + ct ** 3))) ** (1.0 / 3.0)
+                phi0 = W.tanh_droplet(shape, (centre[0], centre[1], 0.5 - Rc * ct), Rc,
+                                      args.delta).astype(np.float32)
+            else:
+                phi0 = phi_sphere
+            slices = []
             sim = capi.Sim(shape, prm)
             sim.set_launch(*launch)
             sim.set_geometry(solid, W.uniform_theta(shape, th))
@@ -320,7 +431,10 @@ def angle_study(args):
                     break
                 zlow = dg.liquid_floor(ph, shape)
                 hist.append(a_sph)
-                print(json.dumps({"angle_study": "progress", "wall_compression": wc, "theta_imposed": th,
+                if args.angle_dump:
+                    slices.append(ph.reshape(nz, ny, nx)[:, ny // 2, :].astype(np.float32))
+                print(json.dumps({"angle_study": "progress", "wall_compression": wc, "ghost_localization": gl,
+                                  "theta_imposed": th,
                                   "steps": steps, "theta_sphere": round(a_sph, 3), "theta_section": round(a_sec, 3),
                                   "fit_R": round(float(Rf), 3), "fit_z0": round(float(c[2]), 3),
                                   "liquid_floor_z": zlow, "umax": umax}), flush=True)
@@ -333,27 +447,67 @@ def angle_study(args):
                     break
             M1 = sim.volume() if status != "non-finite" and not status.startswith("non-finite") else float("nan")
             row = {"angle_study": "result", "shape": list(shape), "R0": args.angle_R, "cz": args.angle_cz,
-                   "delta": args.delta, "D": args.D, "nu": args.nu, "wall_compression": wc, "theta_imposed": th,
+                   "init": args.angle_init, "delta": args.delta, "D": args.D, "nu": args.nu, "wall_compression": wc,
+                   "ghost_localization": gl, "theta_imposed": th,
                    "theta_sphere": round(hist[-1], 3) if hist else None,
                    "theta_section": round(a_sec, 3) if hist else None,
                    "steps": steps, "status": status, "volume_rel_drift": (M1 - M0) / M0,
                    "wall_s": round(time.perf_counter() - t0, 1)}
             rows.append(row)
             print(json.dumps(row), flush=True)
+            if args.angle_dump and slices:
+                os.makedirs(args.angle_dump, exist_ok=True)
+                np.savez_compressed(os.path.join(args.angle_dump, f"xz_wc{wc}_gl{gl}_th{int(th)}.npz"),
+                                    slices=np.stack(slices), every=args.angle_every)
             sim.close()
             del sim
             torch.cuda.empty_cache()
     return rows
 
 
+def rt_log(args):
+    """Wetted radius of the short-time spreading workload (Sec. III B):
+    r = sqrt(sum of phi over the first fluid layer / pi) every `every` steps,
+    against t* = t / tau_i with tau_i = sqrt(rho R0^3 / sigma).  One JSON line
+    per sample."""
+    import torch
+    from paper_2607_25444_amd import capi
+    from paper_2607_25444_amd import tuning
+    from paper_2607_25444_amd import workloads as W
+    from tests import diagnostics as dg
+
+    w = W.spreading_256(args.seed)
+    R0 = 40.0
+    tau = (w.params["rho_l"] * R0 ** 3 / w.params["sigma"]) ** 0.5
+    sim = capi.Sim(w.shape, w.params)
+    sim.set_launch(*tuning.launch_for(w.shape))
+    sim.set_geometry(w.solid, w.theta)
+    sim.set_state(w.phi0)
+    steps = 0
+    while True:
+        phi, _, _ = sim.fields()
+        r = dg.wetted_radius(phi.cpu().numpy(), w.shape)
+        print(json.dumps({"rt_log": w.name, "theta_deg": w.meta.get("theta_deg"), "nu": w.params["nu_l"],
+                          "step": steps, "t_star": round(steps / tau, 5), "r": round(r, 4),
+                          "r_over_R0": round(r / R0, 5)}), flush=True)
+        if steps >= args.rt_steps:
+            break
+        sim.step(args.rt_every)
+        steps += args.rt_every
+    sim.sync()
+    sim.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="spreading", choices=["spreading", "orifice", "porous", "impact", "spreading512", "sessile"])
+    ap.add_argument("--workload", default="orifice",
+                    choices=["spreading", "orifice", "porous", "impact", "spreading512", "sessile"])
+    ap.add_argument("--no-spreading", action="store_true", help="skip the 256x256x128 spreading block")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default=None, help="bx,by,bz,graph,phase_tile")
     ap.add_argument("--batch-steps", type=int, default=200)
@@ -365,13 +519,23 @@ def main():
     ap.add_argument("--no-r1", action="store_true", help="skip the gradient-form collision (collision = 1)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 1 GiB device copy (HBM ceiling; counter calibration)")
+    ap.add_argument("--rt-log", action="store_true",
+                    help="log the wetted radius r(t) of the spreading workload instead of the benchmark")
+    ap.add_argument("--rt-steps", type=int, default=5000)
+    ap.add_argument("--rt-every", type=int, default=50)
     ap.add_argument("--angle-study", action="store_true",
                     help="static contact-angle test of Sec. III A instead of the throughput benchmark")
     ap.add_argument("--angle-shape", default="256,256,256")
     ap.add_argument("--angle-R", type=float, default=40.0)
     ap.add_argument("--angle-cz", type=float, default=2.0, help="droplet centre height (node units)")
+    ap.add_argument("--angle-init", default="sphere", choices=["sphere", "cap"],
+                    help="sphere: the paper's start (about 90 degrees); cap: a cap at the imposed angle "
+                         "with the same liquid volume")
     ap.add_argument("--angles", default="30,60,90,120,150,160")
     ap.add_argument("--wall-compression", default="1", help="comma list of readings of the wall flux")
+    ap.add_argument("--ghost-localization", default="1",
+                    help="comma list: 1 = lambda_s of Eq. (47) in the ghost, 0 = lambda_s = 1 (diagnostic)")
+    ap.add_argument("--angle-dump", default=None, help="folder for the central xz slices of every checkpoint")
     ap.add_argument("--delta", type=float, default=4.0)
     ap.add_argument("--D", type=float, default=0.1)
     ap.add_argument("--nu", type=float, default=0.04)
@@ -397,73 +561,27 @@ def main():
     if args.angle_study:
         angle_study(args)
         return
+    if args.rt_log:
+        rt_log(args)
+        return
 
-    if args.workload == "spreading":
-        w = W.spreading_256(args.seed)
-    elif args.workload == "orifice":
-        w = W.orifice_192(args.seed)
-    elif args.workload == "porous":
-        w = W.porous_256(args.seed)
-    elif args.workload == "impact":
-        w = W.impact_256()
-    elif args.workload == "spreading512":
-        w = W.spreading_512()
-    else:
-        w = W.sessile_32(60.0)
+    w = workload_of(W, args.workload, args.seed)
     launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else tuning.launch_for(w.shape)
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     log(f"[bench] workload {w.name} N={w.N} fluid={w.n_fluid} launch={launch}")
-    sim = capi.Sim(w.shape, w.params, device=dev)
-    sim.set_launch(*launch)
-    sim.set_geometry(w.solid, w.theta)
-    sim.set_state(w.phi0, w.meta.get("u0"))
-    M0 = sim.volume()
-
-    sim.step(args.warmup)
-    sim.sync()
-    stream = sim.stream
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record(stream)
-    sim.step(args.steps)
-    end.record(stream)
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(end)
-    sim.sync()
-    ms_step = ms / max(args.steps, 1)
-    mlups = w.n_fluid * args.steps / (ms * 1e-3) / 1e6
-    log(f"[bench] timed {args.steps} steps: {ms:.2f} ms, {ms_step:.4f} ms/step, {mlups:.1f} MLUPS")
-
-    # per-kernel times from HIP events on the library's stream
-    kp = min(args.steps, 100)
-    kms = sim.profile_step(kp)
-    kavg = [v / kp for v in kms]
-    hydro_ms = kavg[1]
-    achieved = w.n_fluid * HYDRO_BYTES_PER_LU / (hydro_ms * 1e-3) / 1e9
+    blk = plain_block(torch, capi, w, launch, args.steps, args.warmup, probes=True)
+    log(f"[bench] {w.name}: {blk['ms_per_step']:.4f} ms/step, {blk['value']:.1f} MLUPS, kernels {blk['kernel_ms']}")
     traffic = measured_traffic(w.name)
-    M1 = sim.volume()
-    log(f"[bench] kernel ms/step W={kavg[0]:.4f} H={kavg[1]:.4f} P={kavg[2]:.4f} V={kavg[3]:.4f}; "
-        f"hydro {achieved:.0f} GB/s; volume drift {(M1 - M0) / M0:.2e}")
-    # achievable ceilings, measured live after the timed region: the
-    # collide-stream's memory access pattern without its arithmetic (27-plane
-    # pull copy, 216 B per node over all nodes; leaves the handle without a
-    # state) and a plain 1 GiB streaming copy
-    pull_ms = sim.pull_copy_probe(20)
-    pull_gbs = w.N * 216 / (pull_ms * 1e-3) / 1e9
-    copy_gbs = copy_probe(torch, reps=10, quiet=True)
-    log(f"[bench] ceilings: pull copy {pull_gbs:.0f} GB/s ({pull_ms:.4f} ms), plain copy {copy_gbs:.0f} GB/s")
-
     rec = {
         "metric": METRIC,
-        "value": round(mlups, 2),
+        "value": blk["value"],
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 5),
+        "ms_per_step": blk["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -474,7 +592,7 @@ def main():
             "path": "plain step (W ghosts, H collide-stream, P CAC update, V volume correction)",
             "nodes": w.N,
             "fluid_nodes": w.n_fluid,
-            "wall_nodes": sim.nwall,
+            "wall_nodes": blk["wall_nodes"],
             "theta_deg": w.meta.get("theta_deg"),
             "seed": args.seed,
             "launch": list(launch),
@@ -483,42 +601,41 @@ def main():
         "roofline": {
             "bound": "hbm",
             "kernel": "k_hydro",
-            "achieved": round(achieved, 1),
+            "achieved": blk["hydro_algorithmic_GBs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "frac": round(blk["hydro_algorithmic_GBs"] / HBM_PEAK_GBS, 4),
             "traffic": traffic,
             "bytes_per_lu": HYDRO_BYTES_PER_LU,
+            "units_per_launch": w.n_fluid,
+            "kernel_ms": blk["kernel_ms"]["H"],
         },
-        "step": {
-            "kernel_ms": {"W": round(kavg[0], 5), "H": round(kavg[1], 5), "P": round(kavg[2], 5),
-                          "V": round(kavg[3], 5)},
-            "algorithmic_GBs": round(w.n_fluid * STEP_BYTES_PER_LU / (ms_step * 1e-3) / 1e9, 1),
-            "frac_of_peak": round(w.n_fluid * STEP_BYTES_PER_LU / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "bytes_per_lu": STEP_BYTES_PER_LU,
-            "mlups_all_nodes": round(w.N * args.steps / (ms * 1e-3) / 1e6, 2),
-            "volume_rel_drift": (M1 - M0) / M0,
-        },
-        "ceilings": {
-            "pull_copy_GBs": round(pull_gbs, 1),
-            "pull_copy_ms": round(pull_ms, 5),
-            "plain_copy_GBs": round(copy_gbs, 1),
-            "hydro_algorithmic_over_pull_copy": round(achieved / pull_gbs, 4),
-            "hydro_measured_over_pull_copy": (round(traffic / (hydro_ms * 1e-3) / 1e9 / pull_gbs, 4)
-                                              if traffic else None),
-        },
+        "step": blk["step"],
+        "ceilings": blk["ceilings"],
     }
-    sim.close()
-    del sim
+    if traffic:
+        rec["ceilings"]["hydro_measured_over_pull_copy"] = round(
+            traffic / (blk["kernel_ms"]["H"] * 1e-3) / 1e9 / blk["ceilings"]["pull_copy_GBs"], 4)
+    if args.workload != "spreading" and not args.no_spreading:
+        log("[bench] spreading 256x256x128 (plain step) ...")
+        ws = W.spreading_256(args.seed)
+        sb = plain_block(torch, capi, ws, tuning.launch_for(ws.shape), args.steps, args.warmup, probes=False)
+        sb["roofline_frac"] = round(sb["hydro_algorithmic_GBs"] / HBM_PEAK_GBS, 4)
+        sb["traffic"] = measured_traffic(ws.name)
+        rec["spreading"] = sb
+        log(f"[bench] spreading {sb['value']} MLUPS, {sb['ms_per_step']} ms/step")
     if not args.no_r1:
-        log("[bench] gradient-form collision on the same workload ...")
-        rec["r1"] = bench_r1(torch, capi, w, launch, args.r1_steps, 20)
-        rec["r1"]["ratio_to_plain"] = round(rec["r1"]["value"] / rec["value"], 4)
+        log("[bench] gradient-form collision on the spreading workload ...")
+        ws = W.spreading_256(args.seed)
+        rec["r1"] = bench_r1(torch, capi, ws, tuning.launch_for(ws.shape), args.r1_steps, 20)
+        plain = rec["spreading"]["value"] if "spreading" in rec else rec["value"]
+        rec["r1"]["ratio_to_plain_same_workload"] = round(rec["r1"]["value"] / plain, 4)
         log(f"[bench] r1 {rec['r1']}")
     if not args.no_batch:
         log("[bench] batched workload ...")
         rec["batched"] = bench_batch(torch, capi, W, args.batch_steps, 10, args.seed)
-        rec["batched"]["ratio_to_plain"] = round(rec["batched"]["value"] / rec["value"], 4)
+        plain = rec["spreading"]["value"] if "spreading" in rec else rec["value"]
+        rec["batched"]["ratio_to_plain_spreading"] = round(rec["batched"]["value"] / plain, 4)
         log(f"[bench] batched {rec['batched']}")
     if not args.no_adjoint:
         log("[bench] adjoint workload ...")
@@ -526,7 +643,7 @@ def main():
         log(f"[bench] adjoint {rec['adjoint']}")
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host ...")
-        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, W)
         log(f"[bench] cpu baseline {rec['cpu_baseline']}")
     print(json.dumps(rec), flush=True)
 

@@ -98,6 +98,21 @@ def test_one_step_all_fields(orc, wc):
     _cmp(g, o, w, orc, 2e-6, 1e-5)
 
 
+@pytest.mark.parametrize("wc", [0, 1])
+def test_plain_ghost_extrapolation_reading(orc, wc):
+    """The diagnostic reading ghost_localization = 0 (lambda_s = 1 in the ghost
+    of Eq. (46)) on the sessile droplet: 1 and 50 steps against the oracle."""
+    w = W.sessile_32(60.0)
+    fl, wall = _masks(w, orc)
+    for steps, tol_phi, tol_rel in ((1, 2e-6, 1e-5), (50, 1e-5, 1e-4)):
+        o = oracle_run(orc, w, steps, wall_compression=wc, ghost_localization=0)
+        g = gpu_run(w, steps, wall_compression=wc, ghost_localization=0)
+        _cmp(g, o, w, orc, tol_phi, tol_rel)
+        # another reading: its ghosts differ from those of Eq. (47)
+        d = oracle_run(orc, w, steps, wall_compression=wc)
+        assert np.abs(d["phi"][wall] - o["phi"][wall]).max() > 1e-3
+
+
 @pytest.mark.parametrize("steps", [0, 1, 5])
 def test_sessile_initial_steps(orc, steps):
     w = W.sessile_32(60.0)
@@ -208,6 +223,50 @@ def test_full_size_one_step(orc, name):
     o = oracle_run(orc, w, 1)
     g = gpu_run(w, 1, launch=tuning.launch_for(w.shape))
     _cmp(g, o, w, orc, 2e-6, 1e-5, with_f=False)
+
+
+def test_scaled_orifice_200_steps(orc):
+    """The orifice workload scaled down (48 x 48 x 96, plate 4 cells thick with
+    a hole of diameter 12, droplet R = 10 just above it, the paper's orifice
+    fluids, g = 2e-4 so that the drop moves within the run, angle 110
+    degrees): 200 steps with F_p, F_nu and F_ext live, phi within 1e-5 and u
+    within 1e-4 of its maximum."""
+    shape = (48, 48, 96)
+    nx, ny, nz = shape
+    solid = W.orifice_plate_mask(shape, 46, 4, 12.0)
+    phi0 = W.tanh_droplet(shape, ((nx - 1) / 2 + 0.3, (ny - 1) / 2 - 0.2, 49.5 + 2.0 + 10.0), 10.0, 6.0)
+    prm = W.default_params(rho_l=1.2, rho_g=0.9, nu_l=0.031, nu_g=0.24, sigma=0.025, delta=6.0,
+                           g=(0.0, 0.0, -2e-4))
+    w = W.Workload("orifice_48x48x96", shape, solid, W.uniform_theta(shape, 110.0), phi0.astype(np.float32), prm, 200)
+    o = oracle_run(orc, w, 200)
+    g = gpu_run(w, 200)
+    fl, wall = _masks(w, orc)
+    N = w.N
+    dphi = np.abs(g["phi"] - o["phi"])
+    uo, ug = o["u"].reshape(3, N)[:, fl], g["u"].reshape(3, N)[:, fl]
+    print("phi err fluid", dphi[fl].max(), "ghost", dphi[wall].max(), "u err", np.abs(ug - uo).max(),
+          "max u", np.abs(uo).max(), flush=True)
+    assert np.abs(uo).max() > 1e-3  # the drop falls and deforms
+    _cmp(g, o, w, orc, 1e-5, 1e-4, with_f=False)
+
+
+def test_full_size_orifice_20_steps(orc):
+    """The benchmark workload, orifice 192 x 192 x 768 (density and viscosity
+    contrast, body force: F_p, F_nu and F_ext live), 20 steps in the launch the
+    benchmark times: phi within 1e-5 and u within 1e-4 of its maximum on every
+    fluid node, p* and every ghost as well."""
+    from paper_2607_25444_amd import tuning
+    w = W.orifice_192(0)
+    print(f"[full size] {w.name} N={w.N}, 20 steps", flush=True)
+    o = oracle_run(orc, w, 20)
+    g = gpu_run(w, 20, launch=tuning.launch_for(w.shape))
+    fl, wall = _masks(w, orc)
+    dphi = np.abs(g["phi"] - o["phi"])
+    N = w.N
+    uo, ug = o["u"].reshape(3, N)[:, fl], g["u"].reshape(3, N)[:, fl]
+    print("phi err fluid", dphi[fl].max(), "ghost", dphi[wall].max(), "u err", np.abs(ug - uo).max(),
+          "max u", np.abs(uo).max(), flush=True)
+    _cmp(g, o, w, orc, 1e-5, 1e-4, with_f=False)
 
 
 def test_512_cubed_lattice():
