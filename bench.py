@@ -80,33 +80,56 @@ def host_cpu_model():
     return "unknown"
 
 
-def cpu_baseline(w, steps, W):
+def cpu_baseline(w, steps, W, capi=None, launch=None):
     """The FP64 oracle on the host: `steps` steps of the benchmark workload on
     all threads, and one step of the 256x256x128 spreading workload on one
-    thread (a bounded sample each)."""
+    thread (a bounded sample each).  With the GPU binding given, the oracle's
+    state after those steps is also the accuracy gate of the benchmark: the
+    GPU path runs the same steps from the same state in the benchmark's launch
+    and must agree on every fluid node (phi within 1e-5, u within 1e-4 of
+    its maximum)."""
     import numpy as np
     import oracle
 
     def timed(wl, n):
         p = oracle.Params(**wl.params)
-        s = oracle.OracleSim.create(wl.shape, wl.solid, wl.theta.astype(np.float64), p, wl.phi0.astype(np.float64))
+        s = oracle.OracleSim.create(wl.shape, wl.solid, wl.theta.astype(np.float64), p, wl.phi0.astype(np.float64),
+                                    u0=wl.meta.get("u0"))
         t0 = time.perf_counter()
         s.step(n)
-        return time.perf_counter() - t0
+        return time.perf_counter() - t0, s
 
     threads = oracle.num_threads()
-    dt = timed(w, steps)
+    dt, o = timed(w, steps)
+    rec = dict(value=round(w.n_fluid * steps / dt / 1e6, 4), unit="MLUPS", cores=threads, kind="oracle",
+               sample=f"{steps} full steps of the {w.name} workload ({w.n_fluid} fluid nodes), FP64, "
+                      f"{dt:.1f} s wall on {threads} threads")
+    if capi is not None:
+        sim = capi.Sim(w.shape, w.params)
+        sim.set_launch(*launch)
+        sim.set_geometry(w.solid, w.theta)
+        sim.set_state(w.phi0, w.meta.get("u0"))
+        sim.step(steps)
+        phi, u, _ = sim.fields()
+        phi, u = phi.cpu().numpy().astype(np.float64), u.cpu().numpy().astype(np.float64)
+        sim.sync()
+        sim.close()
+        fl = w.solid.reshape(-1) == 0
+        uo, ug = o.u.reshape(3, -1)[:, fl], u.reshape(3, -1)[:, fl]
+        dphi = float(np.abs(phi[fl] - o.phi.reshape(-1)[fl]).max())
+        du = float(np.abs(ug - uo).max() / max(np.abs(uo).max(), 1e-30))
+        rec["gate"] = dict(steps=steps, max_abs_dphi=dphi, bound_phi=1e-5, max_rel_du=du, bound_u=1e-4,
+                           passed=bool(dphi <= 1e-5 and du <= 1e-4))
+    del o
     ws = W.spreading_256(0)
     oracle.set_threads(1)
-    dt1 = timed(ws, 1)
+    dt1, _ = timed(ws, 1)
     oracle.set_threads(threads)
-    return dict(value=round(w.n_fluid * steps / dt / 1e6, 4), unit="MLUPS", cores=threads, kind="oracle",
-                sample=f"{steps} full steps of the {w.name} workload ({w.n_fluid} fluid nodes), FP64, "
-                       f"{dt:.1f} s wall on {threads} threads",
-                value_1core=round(ws.n_fluid / dt1 / 1e6, 4),
-                sample_1core=f"1 full step of the {ws.name} workload ({ws.n_fluid} fluid nodes) on 1 thread, "
-                             f"{dt1:.1f} s wall",
-                cpu_model=host_cpu_model(), nproc=os.cpu_count())
+    rec.update(value_1core=round(ws.n_fluid / dt1 / 1e6, 4),
+               sample_1core=f"1 full step of the {ws.name} workload ({ws.n_fluid} fluid nodes) on 1 thread, "
+                            f"{dt1:.1f} s wall",
+               cpu_model=host_cpu_model(), nproc=os.cpu_count())
+    return rec
 
 
 def workload_of(W, name, seed):
@@ -643,7 +666,7 @@ def main():
         log(f"[bench] adjoint {rec['adjoint']}")
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host ...")
-        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, W)
+        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, W, capi, launch)
         log(f"[bench] cpu baseline {rec['cpu_baseline']}")
     print(json.dumps(rec), flush=True)
 

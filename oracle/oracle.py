@@ -37,7 +37,7 @@ class OrcParams(C.Structure):
                 ("sigma", C.c_double), ("delta", C.c_double), ("D", C.c_double), ("g", C.c_double * 3),
                 ("eps_phi", C.c_double), ("eps_n", C.c_double), ("sin_tol", C.c_double),
                 ("cot_max", C.c_double), ("volume_correction", C.c_int), ("wall_compression", C.c_int),
-                ("collision", C.c_int)]
+                ("collision", C.c_int), ("ghost_localization", C.c_int)]
 
 
 @dataclass
@@ -58,6 +58,7 @@ class Params:
     volume_correction: int = 1
     wall_compression: int = 1
     collision: int = 0          # A2 of Eq. (14): 0 local second moment, 1 gradient form of Eq. (15)
+    ghost_localization: int = 1  # lambda_s of Eq. (47) in the ghost (1), or lambda_s = 1 (0, diagnostic)
 
     def c_struct(self) -> OrcParams:
         p = OrcParams()
@@ -69,6 +70,7 @@ class Params:
         p.volume_correction = int(self.volume_correction)
         p.wall_compression = int(self.wall_compression)
         p.collision = int(self.collision)
+        p.ghost_localization = int(self.ghost_localization)
         return p
 
 
@@ -89,6 +91,16 @@ def build_variant(out_path: str, replacements) -> str:
         f.write(src)
     subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-D_GNU_SOURCE",
                     "-o", out_path, csrc, "-lm"], check=True)
+    return out_path
+
+
+def build_native(out_path: str) -> str:
+    """The same source compiled for the host CPU (-O3 -march=native, still
+    without fast-math: ISO C keeps floating-point contraction off, so the
+    arithmetic and its order are those of the default build).  For long
+    reference runs."""
+    subprocess.run(["gcc", "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-D_GNU_SOURCE",
+                    "-o", out_path, _SRC, "-lm"], check=True)
     return out_path
 
 
@@ -142,6 +154,7 @@ def _configure(L):
     L.orc_step.argtypes = [pp, C.c_int, C.c_int, C.c_int, u8p, dp, dp, dp, dp, dp, C.c_double, C.c_int, dp]
     L.orc_step.restype = C.c_int
     L.orc_num_threads.restype = C.c_int
+    L.orc_set_threads.argtypes = [C.c_int]
     return L
 
 
@@ -288,6 +301,11 @@ def volume(params, shape, solid, phistar, M_target):
     p = params.c_struct()
     lib().orc_volume(C.byref(p), nx, ny, nz, _u8(solid), _d(phistar), float(M_target), _d(out), C.byref(lam))
     return out, lam.value
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on."""
+    lib().orc_set_threads(int(n))
 
 
 def num_threads() -> int:

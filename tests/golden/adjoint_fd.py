@@ -16,8 +16,11 @@ This script calls only oracle/ and the seeded input generators.  Usage, with
 DIR a scratch folder:
 
     python tests/golden/adjoint_fd.py target DIR            # phi_T (one oracle run)
-    python tests/golden/adjoint_fd.py run DIR J0,J1,...     # perturbed runs (job ids, 'all' = every job)
+    python tests/golden/adjoint_fd.py run DIR J0,J1,...     # perturbed runs (job ids; all, all-desc)
     python tests/golden/adjoint_fd.py assemble DIR          # writes adjoint_fd_128x128x64.json here
+
+The runs use the oracle compiled for the host CPU (oracle.build_native: the
+same source and arithmetic, -O3 -march=native).
 
 Each oracle run is 1000 steps on 1.05 M fluid nodes (a few minutes on 16
 host cores); jobs are independent and may run in any order or place.
@@ -103,7 +106,12 @@ def cmd_run(dirp, which):
     w, _ = workload_pair()
     phi_t = np.load(os.path.join(dirp, "phi_target.npy"))
     js = jobs(w)
-    ids = range(len(js)) if which == "all" else [int(v) for v in which.split(",")]
+    if which == "all":
+        ids = list(range(len(js)))
+    elif which == "all-desc":  # the same jobs from the other end (a second host)
+        ids = list(range(len(js)))[::-1]
+    else:
+        ids = [int(v) for v in which.split(",")]
     ring, _ = sampled_nodes(w)
     v = direction(len(ring))
     for j in ids:
@@ -154,6 +162,11 @@ def cmd_assemble(dirp):
 if __name__ == "__main__":
     cmd, dirp = sys.argv[1], sys.argv[2]
     os.makedirs(dirp, exist_ok=True)
+    if cmd in ("target", "run"):
+        import ctypes
+        import tempfile
+        lib_path = O.build_native(os.path.join(tempfile.mkdtemp(), "liboracle_native.so"))
+        O._lib = O._configure(ctypes.CDLL(lib_path))
     if cmd == "target":
         cmd_target(dirp)
     elif cmd == "run":

@@ -1,0 +1,63 @@
+"""The adjoint at the stated length of the contact-angle inversion workload:
+128 x 128 x 64 lattice, bottom-wall angle field from four Gaussian bumps,
+hemispherical droplet R = 24, 1000 steps, checkpoints every K = 50.  The
+target is the final phase field of the run at theta_seed (here the GPU's own
+run), the gradient is taken at theta_{seed + 1000}.
+
+Reference: central differences (h = 1e-4 rad) of the FP64 C oracle's loss,
+stored in tests/golden/adjoint_fd_128x128x64.json by
+tests/golden/adjoint_fd.py (which calls only oracle/): one per sampled wall
+node (16 nodes drawn from the annulus around the initial contact line) and
+one along a random direction over those 16 nodes.  Bound: 1e-3 relative per
+node and along the direction; the 4 far-field wall nodes, never reached by the
+interface, have a zero derivative."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2607_25444_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "adjoint_fd_128x128x64.json")
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="finite-difference reference not generated yet")
+def test_gradient_matches_oracle_finite_differences_at_1000_steps():
+    from paper_2607_25444_amd import capi, tuning
+    d = json.load(open(GOLDEN))
+    steps, K = d["steps"], 50
+    w = W.adjoint_128(seed=d["theta_seed_gradient"])
+    theta_t = W.adjoint_128(seed=d["theta_seed_target"]).theta
+    s = capi.Sim(w.shape, w.params)
+    s.set_launch(*tuning.launch_for(w.shape))
+    # target: the run at theta_seed
+    s.set_geometry(w.solid, theta_t)
+    s.set_state(w.phi0)
+    s.step(steps)
+    target, _, _ = s.fields()
+    target = target.clone()
+    # gradient at theta_{seed + 1000}
+    s.set_geometry(w.solid, w.theta)
+    s.set_state(w.phi0)
+    L, dth = s.adjoint(steps, K, target)
+    idx, _, _ = s.wall_nodes()
+    s.sync()
+    s.close()
+    g = dth.cpu().numpy()
+    pos = {int(k): i for i, k in enumerate(idx)}
+    gn = np.array([g[pos[k]] for k in d["nodes"]])
+    fd = np.array(d["fd"])
+    rel = np.abs(gn - fd) / np.abs(fd)
+    print("loss", L, "max |dL/dtheta|", np.abs(g).max())
+    for k, a, b, r in zip(d["nodes"], gn, fd, rel):
+        print(f"wall node {k}: adjoint {a:.6e} fd {b:.6e} rel {r:.2e}")
+    v = np.array(d["direction"])
+    gd = float(np.dot(v, gn))
+    print(f"direction: adjoint {gd:.6e} fd {d['fd_direction']:.6e}")
+    assert np.all(rel <= 1e-3), rel
+    assert abs(gd - d["fd_direction"]) <= 1e-3 * abs(d["fd_direction"])
+    far = np.array([g[pos[k]] for k in d["far_nodes"]])
+    assert np.abs(far).max() <= 1e-6 * np.abs(g).max()

@@ -30,8 +30,20 @@ def test_hydro_traffic_is_reported_only_for_the_kernel_it_was_taken_on():
 
 def test_summaries_exist_and_name_their_commands():
     for name in ("kernel_stats_spreading_256x256x128.md", "hbm_traffic_spreading_256x256x128.md",
+                 "kernel_stats_orifice_192x192x768.md", "hbm_traffic_orifice_192x192x768.md",
                  "kernel_stats_batch64_and_adjoint_128x128x64.md", "hbm_traffic_adjoint_128x128x64.md",
-                 "kernel_stats_r1_spreading_256x256x128.md"):
+                 "kernel_stats_r1_spreading_256x256x128.md", "valu_lds_counters_spreading_256x256x128.md"):
         text = open(os.path.join(PROF, name)).read()
         assert "rocprofv3" in text and "bench.py" in text, name
         assert "| kernel |" in text, name
+
+
+def test_orifice_traffic_is_the_benchmark_workloads():
+    """The benchmark line's workload (orifice 192 x 192 x 768) has its own
+    counter summary, reported while the kernel sources are unchanged."""
+    d = json.load(open(os.path.join(PROF, "hydro_traffic_orifice_192x192x768.json")))
+    t = bench.measured_traffic("orifice_192x192x768")
+    if d["kernel_source_sha256_16"] == bench.kernel_source_hash():
+        assert t is not None and 220 * d["fluid_nodes"] < t < 300 * d["fluid_nodes"]
+    else:
+        assert t is None
