@@ -119,19 +119,31 @@ CAC_HD float muscl_axis_adj(const float (&q)[5], const float (&uu)[5], const flo
 }
 
 // Cotangent of a pulled population f_i from the ten moment cotangents, held as
-// a = (p*, j_x, j_y, j_z), b = (P_xx, P_yy, P_zz, P_xy), c = (P_xz, P_yz).
+// a = (p*, j_x, j_y, j_z), b = (P_xx, P_yy, P_zz, P_xy), c = (P_xz, P_yz):
+// mb_0 + c_i . j-bar + c_i c_i : P-bar.  With rev, the same for the opposite
+// link (c_i -> -c_i flips the odd part only): the population that bounced
+// back from a solid x + c_i.
 template <int I>
-CAC_HD float pop_bar(float4 a, float4 b, float2 c)
+CAC_HD float pop_bar(float4 a, float4 b, float2 c, bool rev = false)
 {
     constexpr int cx = Lat::cx[I], cy = Lat::cy[I], cz = Lat::cz[I];
-    float v = a.x;
-    if constexpr (cx != 0) v += (float)cx * a.y + b.x;
-    if constexpr (cy != 0) v += (float)cy * a.z + b.y;
-    if constexpr (cz != 0) v += (float)cz * a.w + b.z;
-    if constexpr (cx * cy != 0) v += (float)(cx * cy) * b.w;
-    if constexpr (cx * cz != 0) v += (float)(cx * cz) * c.x;
-    if constexpr (cy * cz != 0) v += (float)(cy * cz) * c.y;
-    return v;
+    float e = a.x, l = 0.f;
+    if constexpr (cx != 0) {
+        e += b.x;
+        l += (float)cx * a.y;
+    }
+    if constexpr (cy != 0) {
+        e += b.y;
+        l += (float)cy * a.z;
+    }
+    if constexpr (cz != 0) {
+        e += b.z;
+        l += (float)cz * a.w;
+    }
+    if constexpr (cx * cy != 0) e += (float)(cx * cy) * b.w;
+    if constexpr (cx * cz != 0) e += (float)(cx * cz) * c.x;
+    if constexpr (cy * cz != 0) e += (float)(cy * cz) * c.y;
+    return rev ? e - l : e + l;
 }
 
 // Cotangents of the Hermite coefficients of the post-collision populations
@@ -140,47 +152,70 @@ struct HermBar {
     float ps = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
     float xx = 0.f, yy = 0.f, zz = 0.f, xy = 0.f, xz = 0.f, yz = 0.f;
     float xxy = 0.f, xxz = 0.f, yyx = 0.f, yyz = 0.f, zzx = 0.f, zzy = 0.f, xyz = 0.f;
-    CAC_HD void pin()
-    {
-        CAC_PIN(ps); CAC_PIN(bx); CAC_PIN(by); CAC_PIN(bz);
-        CAC_PIN(xx); CAC_PIN(yy); CAC_PIN(zz); CAC_PIN(xy); CAC_PIN(xz); CAC_PIN(yz);
-        CAC_PIN(xxy); CAC_PIN(xxz); CAC_PIN(yyx); CAC_PIN(yyz); CAC_PIN(zzx); CAC_PIN(zzy); CAC_PIN(xyz);
-    }
 };
 
-// Transpose of the Hermite projection of one post-collision population
+// Transpose of the Hermite projection of the post-collision populations
 // f*_i = w_i [ps + 3 c.b + 4.5 (cc : C2 - tr C2 / 3) + 4.5 H3 : C3] (herm_pair):
-// adds fb * d f*_i / d (coefficients).
-template <int I>
-CAC_HD void proj_add(float fb, HermBar &h)
-{
-    constexpr float cx = (float)Lat::cx[I], cy = (float)Lat::cy[I], cz = (float)Lat::cz[I];
-    constexpr float w = Lat::w(I);
-    constexpr float t2 = 4.5f * w;
-    constexpr float hx = cx * cx - 1.0f / 3.0f, hy = cy * cy - 1.0f / 3.0f, hz = cz * cz - 1.0f / 3.0f;
-    h.ps += w * fb;
-    h.xx += (t2 * hx) * fb;  // cc : C2 - tr/3 = sum_a (c_a^2 - 1/3) C2_aa + off-diagonal terms
-    h.yy += (t2 * hy) * fb;
-    h.zz += (t2 * hz) * fb;
-    if constexpr (cx * cy != 0.0f) h.xy += (2.0f * t2 * cx * cy) * fb;
-    if constexpr (cx * cz != 0.0f) h.xz += (2.0f * t2 * cx * cz) * fb;
-    if constexpr (cy * cz != 0.0f) h.yz += (2.0f * t2 * cy * cz) * fb;
-    if constexpr (cx != 0.0f) h.bx += (3.0f * w * cx) * fb;
-    if constexpr (cy != 0.0f) h.by += (3.0f * w * cy) * fb;
-    if constexpr (cz != 0.0f) h.bz += (3.0f * w * cz) * fb;
-    if constexpr (hx * cy != 0.0f) h.xxy += (3.0f * t2 * hx * cy) * fb;
-    if constexpr (hx * cz != 0.0f) h.xxz += (3.0f * t2 * hx * cz) * fb;
-    if constexpr (hy * cx != 0.0f) h.yyx += (3.0f * t2 * hy * cx) * fb;
-    if constexpr (hy * cz != 0.0f) h.yyz += (3.0f * t2 * hy * cz) * fb;
-    if constexpr (hz * cx != 0.0f) h.zzx += (3.0f * t2 * hz * cx) * fb;
-    if constexpr (hz * cy != 0.0f) h.zzy += (3.0f * t2 * hz * cy) * fb;
-    if constexpr (cx * cy * cz != 0.0f) h.xyz += (6.0f * t2 * cx * cy * cz) * fb;
-}
+// h = sum_i fb_i d f*_i / d (coefficients), summed over the 27 links by
+// moments.  The D3Q27 weights factorise, w_i = w1(cx) w1(cy) w1(cz) with
+// w1(0) = 2/3 and w1(+-1) = 1/6, so h is a linear map of the 17 moments
+// M_abc = sum_i w_i cx^a cy^b cz^c fb_i that it needs, and each x-line of
+// links (cy, cz fixed) enters them through three partial sums over cx.
+// Moment order in M: 000 100 010 001 200 020 002 110 101 011 210 201 120 021
+// 102 012 111.
+struct HermMoments {
+    float M[17] = {};
+    static constexpr int A[17] = {0, 1, 0, 0, 2, 0, 0, 1, 1, 0, 2, 2, 1, 0, 1, 0, 1};
+    static constexpr int B[17] = {0, 0, 1, 0, 0, 2, 0, 1, 0, 1, 1, 0, 2, 2, 0, 1, 1};
+    static constexpr int C[17] = {0, 0, 0, 1, 0, 0, 2, 0, 1, 1, 0, 1, 0, 1, 2, 2, 1};
+    static constexpr float pw(int v, int e) { return e == 0 ? 1.0f : e == 1 ? (float)v : (float)(v * v); }
+    static constexpr float w1(int v) { return v == 0 ? 2.0f / 3.0f : 1.0f / 6.0f; }
+    // one x-line: fb at cx = -1, 0, +1
+    template <int CY, int CZ>
+    CAC_HD void add_line(float gm, float g0, float gp)
+    {
+        const float S = gp + gm, D = gp - gm;
+        const float A0 = 4.0f * g0 + S;  // 6 sum_cx w1(cx) fb; D and S likewise for cx^1, cx^2
+        static_for<17>([&](auto K) {
+            constexpr int k = K;
+            constexpr float cf = w1(CY) * w1(CZ) * (1.0f / 6.0f) * pw(CY, B[k]) * pw(CZ, C[k]);
+            if constexpr (cf != 0.0f) M[k] += cf * (A[k] == 0 ? A0 : A[k] == 1 ? D : S);
+        });
+    }
+    CAC_HD void pin()
+    {
+#pragma unroll
+        for (int k = 0; k < 17; ++k) CAC_PIN(M[k]);
+    }
+    CAC_HD HermBar herm() const
+    {
+        HermBar h;
+        const float t = 1.0f / 3.0f;
+        h.ps = M[0];
+        h.bx = 3.0f * M[1];
+        h.by = 3.0f * M[2];
+        h.bz = 3.0f * M[3];
+        h.xx = 4.5f * (M[4] - t * M[0]);
+        h.yy = 4.5f * (M[5] - t * M[0]);
+        h.zz = 4.5f * (M[6] - t * M[0]);
+        h.xy = 9.0f * M[7];
+        h.xz = 9.0f * M[8];
+        h.yz = 9.0f * M[9];
+        h.xxy = 13.5f * (M[10] - t * M[2]);
+        h.xxz = 13.5f * (M[11] - t * M[3]);
+        h.yyx = 13.5f * (M[12] - t * M[1]);
+        h.yyz = 13.5f * (M[13] - t * M[3]);
+        h.zzx = 13.5f * (M[14] - t * M[1]);
+        h.zzy = 13.5f * (M[15] - t * M[2]);
+        h.xyz = 27.0f * M[16];
+        return h;
+    }
+};
 
 // Transpose of the collision of hydro_node at one fluid node.
 // mom: moments (p*, j, P) of the pulled populations; (gx, gy, gz, lap, ph):
 // phi-hat gradient, Laplacian and value; hb: cotangents of the Hermite
-// coefficients of the post-collision populations (proj_add); (ubx, uby, ubz):
+// coefficients of the post-collision populations (HermMoments); (ubx, uby, ubz):
 // cotangent of the velocity output.  Writes the moment cotangents mb and adds
 // the cotangents of ph, of the gradient and of the Laplacian.
 CAC_HD void collide_adj(const DevParams &p, const float (&mom)[10], float gx, float gy, float gz, float lap, float ph,
@@ -522,23 +557,34 @@ CAC_HD void adj_main_node(const Grid &g, const DevParams &p, const AdjStep &S, i
     const float2 *mC = reinterpret_cast<const float2 *>(S.mb_in + 8u * N);
     const float4 a0 = mA[n], b0 = mB[n];
     const float2 c0 = mC[n];
-    HermBar hb;
-    proj_add<0>(a0.x, hb);
-    static_for<26>([&](auto J) {
-        constexpr int i = J + 1;
-        constexpr int oi = Lat::opp(i);
-        // both candidates are formed and the wall bit selects (the neighbour index is valid either way)
-        const uint32_t id = at<Lat::cx[i], Lat::cy[i], Lat::cz[i]>(o);
+    // cotangent of each pulled population from the node it came from: x + c_i,
+    // or x itself with the link reversed when x + c_i is solid (bounce-back)
+    auto fbar = [&](auto Ic) -> float {
+        constexpr int i = Ic;
         constexpr bool needc = Lat::cz[i] != 0 && (Lat::cx[i] != 0 || Lat::cy[i] != 0);
+        const bool rev = ((m >> i) & 1u) != 0;
+        const uint32_t id = rev ? n : at<Lat::cx[i], Lat::cy[i], Lat::cz[i]>(o);
         const float2 ci = needc ? mC[id] : make_float2(0.f, 0.f);
-        const float vn = pop_bar<i>(mA[id], mB[id], ci);
-        const float vw = pop_bar<oi>(a0, b0, c0);
-        proj_add<i>(((m >> i) & 1u) ? vw : vn, hb);
-        if constexpr (i % 5 == 0) {
-            hb.pin();
+        return pop_bar<i>(mA[id], mB[id], ci, rev);
+    };
+    HermMoments hm;
+    static_for<9>([&](auto Lc) {
+        constexpr int cy = (int)Lc % 3 - 1, cz = (int)Lc / 3 - 1;
+        constexpr int im = Lat::idx(-1, cy, cz), i0 = Lat::idx(0, cy, cz), ip = Lat::idx(1, cy, cz);
+        const float gm = fbar(std::integral_constant<int, im>{});
+        const float gp = fbar(std::integral_constant<int, ip>{});
+        float g0;
+        if constexpr (i0 == 0)
+            g0 = a0.x;  // the rest population stays at the node
+        else
+            g0 = fbar(std::integral_constant<int, i0>{});
+        hm.add_line<cy, cz>(gm, g0, gp);
+        if constexpr ((int)Lc % 2 == 1) {
+            hm.pin();
             CAC_SCHED_FENCE();
         }
     });
+    const HermBar hb = hm.herm();
     CAC_SCHED_FENCE();
     float mbo[10];
     collide_adj(p, mom, gx, gy, gz, lap, ph, hb, ub[0], ub[1], ub[2], mbo, phb, Gbx, Gby, Gbz, lapb);

@@ -177,6 +177,7 @@ cac_status replay_step(cac_handle *h, AdjTape &T, int k, int j, hipStream_t st)
 {
     Fields F = h->F;
     F.theta = T.theta;
+    F.chunk = nullptr;  // the out-of-place correction below visits every node
     F.phi[0] = T.rphi[k][j + 1];
     F.phi[1] = T.rphi[k][j];
     HIPCHK(h, launch_ghost(h->g, h->dp, F, 0, st));

@@ -127,7 +127,7 @@ __global__ __launch_bounds__(BX *BY) void k_bphase(BatchPtrs B, const BatchDomai
         const BatchDomain d = dom[dt.x];
         const DomPtrs P = domain_ptrs(B, d, cur);
         phase_tile<BX, BY>(d.g, d.pt, d.p, dt.y, P.phi_cur, P.phi_oth, P.u, P.a, P.solid,
-                           B.partial + d.p_item0 + dt.y, B.flag);
+                           B.partial + d.p_item0 + dt.y, B.flag, B.chunk, d.off);
     }
 }
 
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(BX *BY) void k_bphase1(BatchPtrs B, const BatchDoma
     const BatchDomain d = dom[dt.x];
     const DomPtrs P = domain_ptrs(B, d, cur);
     phase_tile<BX, BY>(d.g, d.pt, d.p, dt.y, P.phi_cur, P.phi_oth, P.u, P.a, P.solid, B.partial + d.p_item0 + dt.y,
-                       B.flag);
+                       B.flag, B.chunk, d.off);
 }
 
 // One workgroup per domain: lambda_k from its tile partials in a fixed order.
@@ -167,13 +167,21 @@ __global__ __launch_bounds__(256) void k_bvol_finalize(BatchPtrs B, const BatchD
 
 // phi <- phi* + lambda_k chi(phi*) on fluid nodes (Eq. (53)), four consecutive
 // nodes of the concatenated arrays per thread (VEC: 16-byte phi and 4-byte
-// mask loads).  The domain of the first node comes from a host-built table of
-// the domain of each 256-node block; a later node past the domain's end
-// belongs to a following domain (quads straddle domains only at their
-// boundaries).  The population and mask loads do not depend on the lookup.
+// mask loads).  A workgroup covers one 1024-node chunk; when the phase update
+// wrote no interface node there (chunk byte clear) it returns at once, else it
+// clears the byte for the next step.  The domain of the first node comes from
+// a host-built table of the domain of each 256-node block; a later node past
+// the domain's end belongs to a following domain (quads straddle domains only
+// at their boundaries).  The population and mask loads do not depend on the
+// lookup.
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_bvol_apply(BatchPtrs B, const BatchDomain *__restrict__ dom, int cur_next)
 {
+    if (B.chunk) {
+        if (!B.chunk[blockIdx.x]) return;  // the same for the whole workgroup
+        __syncthreads();                    // every thread has read the byte before it is cleared
+        if (threadIdx.x == 0) B.chunk[blockIdx.x] = 0;
+    }
     const uint32_t n0 = 4u * (blockIdx.x * 256u + threadIdx.x);
     if (n0 >= B.ntot) return;
     float *phi = cur_next ? B.phi[1] : B.phi[0];

@@ -455,6 +455,7 @@ cac_status cac_batch_init(cac_batch **bp, int ndom, const cac_domain_desc *d, ca
     B.partial = (double2 *)balloc(b, (ptiles + 64) * sizeof(double2));
     B.scal = (double *)balloc(b, 8 * (size_t)ndom * sizeof(double));
     B.flag = (uint32_t *)balloc(b, 256);
+    B.chunk = (uint8_t *)balloc(b, (N + 1023) / 1024);
     b->d_dom = (BatchDomain *)balloc(b, ndom * sizeof(BatchDomain));
     uint32_t *d_start = (uint32_t *)balloc(b, (ndom + 1) * sizeof(uint32_t));
     const size_t nblk = (N + 255) / 256;
@@ -462,7 +463,7 @@ cac_status cac_batch_init(cac_batch **bp, int ndom, const cac_domain_desc *d, ca
     b->pstar0 = (float *)balloc(b, N * sizeof(float));
     b->mass_partial = (double2 *)balloc(b, (maxN / 256 + 64) * sizeof(double2));
     if (!B.f[0] || !B.f[1] || !B.phi[0] || !B.phi[1] || !B.u || !B.a || !B.nbr || !B.solid || !B.wall_idx ||
-        !B.wall_q || !B.wall_n || !B.theta || !B.wall_dom || !B.partial || !B.scal || !B.flag || !b->d_dom ||
+        !B.wall_q || !B.wall_n || !B.theta || !B.wall_dom || !B.partial || !B.scal || !B.flag || !B.chunk || !b->d_dom ||
         !b->pstar0 || !b->mass_partial || !d_start || !d_blk)
         return bail(CAC_ERR_ALLOC);
     B.dom = b->d_dom;
@@ -497,6 +498,7 @@ cac_status cac_batch_init(cac_batch **bp, int ndom, const cac_domain_desc *d, ca
         hipMemsetAsync(B.a, 0, 3 * N * sizeof(float), s) != hipSuccess ||
         hipMemsetAsync(b->pstar0, 0, N * sizeof(float), s) != hipSuccess ||
         hipMemsetAsync(B.flag, 0, 256, s) != hipSuccess ||
+        hipMemsetAsync(B.chunk, 0, (N + 1023) / 1024, s) != hipSuccess ||
         hipMemsetAsync(B.scal, 0, 8 * (size_t)ndom * sizeof(double), s) != hipSuccess)
         return bail(CAC_ERR_HIP);
     for (int k = 0; k < ndom; ++k) {

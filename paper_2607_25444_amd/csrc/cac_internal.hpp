@@ -96,6 +96,7 @@ struct Fields {
     double2 *partial;   // per-tile (sum phi*, sum chi)
     double *scal;       // [0] M_target, [1] lambda, [2] M*, [3] W
     uint32_t *flag;     // watchdog: nonzero after a non-finite value
+    uint8_t *chunk;     // per 1024 nodes: set by P where it wrote an interface node, cleared by V
     float *pstar0;      // p* of the initial state (reported before the first step)
     int nwall;
 };
@@ -124,6 +125,7 @@ struct BatchPtrs {
     double2 *partial;    // per phase tile, at BatchDomain::p_item0 + tile
     double *scal;        // 8 per domain: [0] M_target, [1] lambda, [2] M*, [3] W, [4] volume
     uint32_t *flag;
+    uint8_t *chunk;      // per 1024 nodes of the concatenated arrays: set by P at interface nodes, cleared by V
     const BatchDomain *dom;
     const uint32_t *dom_start;  // ndom + 1 node offsets: domain k holds nodes [dom_start[k], dom_start[k + 1])
     const uint16_t *blk_dom;    // domain of the first node of each 256-node block of the concatenated arrays

@@ -53,10 +53,11 @@ template <int BX, int BY>
 __global__ __launch_bounds__(BX *BY) void k_phase(Grid g, PhaseTiling pt, DevParams p, const float *__restrict__ phi,
                                                   float *__restrict__ phi_out, const float *__restrict__ u,
                                                   const float *__restrict__ aw, const uint8_t *__restrict__ solid,
-                                                  double2 *__restrict__ partial, uint32_t *__restrict__ flag)
+                                                  double2 *__restrict__ partial, uint32_t *__restrict__ flag,
+                                                  uint8_t *__restrict__ chunk)
 {
     const uint32_t tile = xcd_tile(p.rev_order ? gridDim.x - 1u - blockIdx.x : blockIdx.x, pt.ntiles);
-    phase_tile<BX, BY>(g, pt, p, tile, phi, phi_out, u, aw, solid, partial + tile, flag);
+    phase_tile<BX, BY>(g, pt, p, tile, phi, phi_out, u, aw, solid, partial + tile, flag, chunk);
 }
 
 // Debug: quiet NaNs into every value the step must never read -- populations
@@ -111,31 +112,69 @@ __global__ __launch_bounds__(1024) void k_vol_finalize(const double2 *__restrict
     }
 }
 
-// phi^{n+1} = phi* + lambda chi(phi*) on fluid nodes (Eq. (53)).  Four
-// consecutive nodes per thread; VEC: one 16-byte phi load and one 4-byte mask
-// load (both buffers 16-byte aligned).  Only interface nodes are stored.
+// The volume correction in one pass.  Each workgroup covers 1024 nodes (four
+// per thread).  lambda = (M_target - M*) / W when W > 0 (Eqs. (49)-(55)),
+// from the per-tile partials summed in a fixed order: every workgroup that
+// needs it forms the same sum itself, so no second launch orders a finalize
+// before the update; workgroup 0 stores lambda, M* and W.  Then
+// phi^{n+1} = phi* + lambda chi(phi*) on the interface fluid nodes (Eq. (53)).
+// A workgroup whose chunk byte is clear holds no interface node (the phase
+// update sets the byte of every node it counts in W) and returns at once; a
+// set byte is cleared for the next step.  With chunk == nullptr every
+// workgroup updates its nodes.  VEC: one 16-byte phi load and one 4-byte
+// mask load per thread (both buffers 16-byte aligned).  Only interface nodes
+// are stored.
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_vol_apply(uint32_t N, const uint8_t *__restrict__ solid,
-                                                   float *__restrict__ phi, const double *__restrict__ scal,
-                                                   float eps_phi)
+                                                   float *__restrict__ phi, const double2 *__restrict__ partial,
+                                                   uint32_t np, double *__restrict__ scal, int vc, float eps_phi,
+                                                   uint8_t *__restrict__ chunk)
 {
-    const uint32_t n0 = 4u * (blockIdx.x * 256u + threadIdx.x);
-    if (n0 >= N) return;
-    const double lam = scal[1];
-    auto one = [&](uint32_t n, uint8_t s, float v) {
-        if (!s && v > eps_phi && v < 1.0f - eps_phi)
-            phi[n] = (float)((double)v + lam * ((double)v * (1.0 - (double)v)));
-    };
-    if (VEC && n0 + 4u <= N) {
-        const uchar4 s = *reinterpret_cast<const uchar4 *>(solid + n0);
-        const float4 v = *reinterpret_cast<const float4 *>(phi + n0);
-        one(n0, s.x, v.x);
-        one(n0 + 1u, s.y, v.y);
-        one(n0 + 2u, s.z, v.z);
-        one(n0 + 3u, s.w, v.w);
+    const uint32_t b = blockIdx.x;
+    const bool live = chunk == nullptr || chunk[b] != 0;
+    if (!live && b != 0) return;
+    // the node loads do not depend on lambda: issued with the partials
+    const uint32_t n0 = 4u * (b * 256u + threadIdx.x);
+    const int cnt = live && n0 < N ? (int)min(4u, N - n0) : 0;
+    uint8_t s[4] = {1, 1, 1, 1};
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
+    if (VEC && cnt == 4) {
+        const uchar4 s4 = *reinterpret_cast<const uchar4 *>(solid + n0);
+        const float4 v4 = *reinterpret_cast<const float4 *>(phi + n0);
+        s[0] = s4.x, s[1] = s4.y, s[2] = s4.z, s[3] = s4.w;
+        v[0] = v4.x, v[1] = v4.y, v[2] = v4.z, v[3] = v4.w;
     } else {
-        for (uint32_t n = n0; n < min(n0 + 4u, N); ++n) one(n, solid[n], phi[n]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k < cnt) {
+                s[k] = solid[n0 + k];
+                v[k] = phi[n0 + k];
+            }
     }
+    double x = 0.0, y = 0.0;
+    for (uint32_t k = threadIdx.x; k < np; k += 256u) {
+        const double2 pk = partial[k];
+        x += pk.x;
+        y += pk.y;
+    }
+    block_sum2<256>(x, y);
+    __shared__ double slam;
+    if (threadIdx.x == 0) {
+        const double l = (vc && y > 0.0) ? (scal[0] - x) / y : 0.0;
+        slam = l;
+        if (b == 0) {
+            scal[1] = l;
+            scal[2] = x;
+            scal[3] = y;
+        }
+        if (live && chunk) chunk[b] = 0;
+    }
+    __syncthreads();
+    const double lam = slam;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (k < cnt && !s[k] && v[k] > eps_phi && v[k] < 1.0f - eps_phi)
+            phi[n0 + k] = (float)((double)v[k] + lam * ((double)v[k] * (1.0 - (double)v[k])));
 }
 
 // Out-of-place correction used when the forward sweep is recorded: phi* stays
@@ -347,7 +386,7 @@ hipError_t launch_phase(const Grid &g, const Tiling &t, const DevParams &p, cons
 #define CAC_PHASE(BX_, BY_)                                                                                           \
     if (bx == BX_ && by == BY_) {                                                                                     \
         k_phase<BX_, BY_><<<pt.ntiles, BX_ * BY_, 0, s>>>(g, pt, p, F.phi[pcur], F.phi[pcur ^ 1], F.u, F.a, F.solid, \
-                                                          F.partial, F.flag);                                         \
+                                                          F.partial, F.flag, F.chunk);                                \
         return hipGetLastError();                                                                                     \
     }
     CAC_PHASE(64, 8)
@@ -363,14 +402,15 @@ hipError_t launch_phase(const Grid &g, const Tiling &t, const DevParams &p, cons
 hipError_t launch_volume(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, int pnext,
                          hipStream_t s)
 {
-    k_vol_finalize<<<1, 1024, 0, s>>>(F.partial, phase_tiles(g, t), F.scal, p.volume_correction);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const unsigned nb = blocks_for(blocks_for(g.N, 4), 256);
+    // one workgroup per 1024 nodes: chunk k of the phase update is workgroup k
+    const unsigned nb = blocks_for(g.N, 1024);
+    const uint32_t np = phase_tiles(g, t);
     if ((((uintptr_t)F.solid | (uintptr_t)F.phi[pnext]) & 15u) == 0)
-        k_vol_apply<true><<<nb, 256, 0, s>>>(g.N, F.solid, F.phi[pnext], F.scal, p.eps_phi);
+        k_vol_apply<true><<<nb, 256, 0, s>>>(g.N, F.solid, F.phi[pnext], F.partial, np, F.scal, p.volume_correction,
+                                             p.eps_phi, F.chunk);
     else
-        k_vol_apply<false><<<nb, 256, 0, s>>>(g.N, F.solid, F.phi[pnext], F.scal, p.eps_phi);
+        k_vol_apply<false><<<nb, 256, 0, s>>>(g.N, F.solid, F.phi[pnext], F.partial, np, F.scal,
+                                              p.volume_correction, p.eps_phi, F.chunk);
     return hipGetLastError();
 }
 

@@ -338,14 +338,17 @@ cac_status cac_init(cac_handle **hp, int nx, int ny, int nz, const cac_params *p
     F.partial = (double2 *)dev_alloc(h, h->partial_cap * sizeof(double2));
     F.scal = (double *)dev_alloc(h, 8 * sizeof(double));
     F.flag = (uint32_t *)dev_alloc(h, 256);
+    const size_t nchunk = (Nf + 1023) / 1024;
+    F.chunk = (uint8_t *)dev_alloc(h, nchunk);
     if (!F.f[0] || !F.f[1] || !F.phi[0] || !F.phi[1] || !F.u || !F.a || !F.nbr || !F.solid || !F.pstar0 ||
-        !F.partial || !F.scal || !F.flag) {
+        !F.partial || !F.scal || !F.flag || !F.chunk) {
         for (void *q : h->owned) (void)hipFree(q);
         delete h;
         return CAC_ERR_ALLOC;
     }
     if (hipMemsetAsync(F.flag, 0, 256, h->stream) != hipSuccess ||
-        hipMemsetAsync(F.scal, 0, 8 * sizeof(double), h->stream) != hipSuccess) {
+        hipMemsetAsync(F.scal, 0, 8 * sizeof(double), h->stream) != hipSuccess ||
+        hipMemsetAsync(F.chunk, 0, nchunk, h->stream) != hipSuccess) {
         for (void *q : h->owned) (void)hipFree(q);
         delete h;
         return CAC_ERR_HIP;

@@ -573,14 +573,18 @@ __device__ __forceinline__ float muscl_axis(float q0, float q1, float q2, float 
 }
 
 // One (column tile, z-chunk) of the phase update; the workgroup's FP64 sums
-// go to *partial_out (written by thread 0).  Must be entered by the whole
-// workgroup; reuses its LDS on every call.
+// go to *partial_out (written by thread 0).  With `chunk` given, every node
+// that enters the interface sum also sets the byte of its 1024-node chunk
+// there, counted from node offset `coff` (the volume correction touches no
+// other chunk).  Must be entered by the whole workgroup; reuses its LDS on
+// every call.
 template <int BX, int BY>
 __device__ __forceinline__ void phase_tile(const Grid &g, const PhaseTiling &pt, const DevParams &p, uint32_t tile,
                                            const float *__restrict__ phi, float *__restrict__ phi_out,
                                            const float *__restrict__ u, const float *__restrict__ aw,
                                            const uint8_t *__restrict__ solid, double2 *partial_out,
-                                           uint32_t *__restrict__ flag)
+                                           uint32_t *__restrict__ flag, uint8_t *__restrict__ chunk,
+                                           uint32_t coff = 0u)
 {
     constexpr int NT = BX * BY;
     constexpr int HX = BX + 4, HY = BY + 4;  // phi plane, halo 2
@@ -877,7 +881,10 @@ __device__ __forceinline__ void phase_tile(const Grid &g, const PhaseTiling &pt,
             at_byte(phi_out + (uint32_t)z * g.nxny, cxy) = ps;
             if (!isfinite(ps)) flag[0] = 1u;
             sphis += (double)ps;
-            if (ps > p.eps_phi && ps < 1.0f - p.eps_phi) schi += (double)ps * (1.0 - (double)ps);
+            if (ps > p.eps_phi && ps < 1.0f - p.eps_phi) {
+                schi += (double)ps * (1.0 - (double)ps);
+                if (chunk) chunk[(coff + (uint32_t)z * g.nxny + (cxy >> 2)) >> 10] = 1;
+            }
         }
         // roll the column state to plane z+1
         tq_m = tq_c;

@@ -16,7 +16,8 @@ This script calls only oracle/ and the seeded input generators.  Usage, with
 DIR a scratch folder:
 
     python tests/golden/adjoint_fd.py target DIR            # phi_T (one oracle run)
-    python tests/golden/adjoint_fd.py run DIR J0,J1,...     # perturbed runs (job ids; all, all-desc)
+    python tests/golden/adjoint_fd.py run DIR J0,J1,... [SECONDS]  # perturbed runs (job ids; all,
+                                                            # all-desc); stop before a job would pass SECONDS
     python tests/golden/adjoint_fd.py assemble DIR          # writes adjoint_fd_128x128x64.json here
 
 The runs use the oracle compiled for the host CPU (oracle.build_native: the
@@ -81,15 +82,17 @@ def jobs(w):
     return out
 
 
-def forward(w, theta):
+def forward(w, theta, tag=""):
     o = O.OracleSim.create(w.shape, w.solid, np.asarray(theta, np.float64), O.Params(**w.params),
                            w.phi0.astype(np.float64))
-    o.step(STEPS)
+    for done in range(0, STEPS, 250):
+        o.step(250)
+        print(f"  {tag} step {done + 250}", flush=True)
     return o.phi
 
 
-def loss(w, theta, phi_t):
-    phi = forward(w, theta)
+def loss(w, theta, phi_t, tag=""):
+    phi = forward(w, theta, tag)
     d = (phi - phi_t)[w.solid == 0]
     return 0.5 * float(np.dot(d, d))
 
@@ -102,7 +105,7 @@ def cmd_target(dirp):
     print(f"target: {time.time() - t0:.1f} s, {O.num_threads()} threads", flush=True)
 
 
-def cmd_run(dirp, which):
+def cmd_run(dirp, which, budget_s=None):
     w, _ = workload_pair()
     phi_t = np.load(os.path.join(dirp, "phi_target.npy"))
     js = jobs(w)
@@ -114,10 +117,14 @@ def cmd_run(dirp, which):
         ids = [int(v) for v in which.split(",")]
     ring, _ = sampled_nodes(w)
     v = direction(len(ring))
+    start, last = time.time(), 0.0
     for j in ids:
         path = os.path.join(dirp, f"job_{j:03d}.json")
         if os.path.exists(path):
             continue
+        if budget_s is not None and time.time() - start + 1.1 * last > budget_s:
+            print(f"time budget of {budget_s} s reached before job {j}", flush=True)
+            break
         kind, node, sign = js[j]
         th = np.asarray(w.theta, np.float64).copy()
         if kind == "node":
@@ -125,7 +132,8 @@ def cmd_run(dirp, which):
         else:
             th[ring] += sign * H * v
         t0 = time.time()
-        L = loss(w, th, phi_t)
+        L = loss(w, th, phi_t, f"job {j}")
+        last = time.time() - t0
         with open(path, "w") as f:
             json.dump({"job": j, "kind": kind, "node": node, "sign": sign, "loss": L}, f)
         print(f"job {j} ({kind} {node} {sign:+d}): L = {L:.17g}, {time.time() - t0:.1f} s, "
@@ -170,7 +178,7 @@ if __name__ == "__main__":
     if cmd == "target":
         cmd_target(dirp)
     elif cmd == "run":
-        cmd_run(dirp, sys.argv[3])
+        cmd_run(dirp, sys.argv[3], float(sys.argv[4]) if len(sys.argv) > 4 else None)
     elif cmd == "assemble":
         cmd_assemble(dirp)
     else:
