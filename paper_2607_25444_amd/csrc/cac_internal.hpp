@@ -97,6 +97,7 @@ struct Fields {
     double *scal;       // [0] M_target, [1] lambda, [2] M*, [3] W
     uint32_t *flag;     // watchdog: nonzero after a non-finite value
     uint8_t *chunk;     // per 1024 nodes: set by P where it wrote an interface node, cleared by V
+    uint8_t *twall;     // per hydrodynamic tile: 1 when a node of the tile is solid or next to a solid node
     float *pstar0;      // p* of the initial state (reported before the first step)
     int nwall;
 };
@@ -164,6 +165,7 @@ hipError_t launch_phase(const Grid &g, const Tiling &t, const DevParams &p, cons
                         hipStream_t s);
 uint32_t phase_tiles(const Grid &g, const Tiling &t);  // workgroups (and FP64 partials) of the phase kernel
 uint32_t phase_tiles_max(const Grid &g);                // over every phase tile shape
+hipError_t launch_tile_walls(const Grid &g, const Tiling &t, const Fields &F, hipStream_t s);
 hipError_t launch_volume(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F, int pnext,
                          hipStream_t s);
 hipError_t launch_poison(const Grid &g, const Fields &F, hipStream_t s);  // debug (k_poison)

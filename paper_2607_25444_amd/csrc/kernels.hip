@@ -37,8 +37,8 @@ __global__ __launch_bounds__(256) void k_ghost(Grid g, DevParams p, const int32_
 template <int NT, bool NTL>
 __global__ __launch_bounds__(NT) void k_hydro(Grid g, Tiling t, DevParams p, const float *__restrict__ fin,
                                               float *__restrict__ fout, const float *__restrict__ phi,
-                                              const uint32_t *__restrict__ nbr, float *__restrict__ u,
-                                              uint32_t *__restrict__ flag)
+                                              const uint32_t *__restrict__ nbr, const uint8_t *__restrict__ twall,
+                                              float *__restrict__ u, uint32_t *__restrict__ flag)
 {
     // Workgroup order: with non-temporal loads nothing is re-read from L2, and
     // the hardware's round-robin over the XCDs streams HBM best (3% faster on
@@ -46,7 +46,20 @@ __global__ __launch_bounds__(NT) void k_hydro(Grid g, Tiling t, DevParams p, con
     // tiles so that halo rows stay in its L2.
     const uint32_t b = p.rev_order ? gridDim.x - 1u - blockIdx.x : blockIdx.x;
     const uint32_t tile = NTL ? b : xcd_tile(b, t.ntiles);
-    hydro_node<NTL>(g, p, tile_node(g, t, tile), fin, fout, phi, nbr, u, flag);
+    // tiles away from every solid node skip the neighbour-mask load (4 B per node)
+    hydro_node<NTL>(g, p, tile_node(g, t, tile), fin, fout, phi, nbr, u, flag, twall[tile] != 0);
+}
+
+// Per hydrodynamic tile: 1 when a node of the tile is solid or has a solid
+// neighbour (its neighbour mask is nonzero), else 0.  One workgroup per tile,
+// in the tiling of the hydrodynamic kernel.
+__global__ __launch_bounds__(512) void k_tile_walls(Grid g, Tiling t, const uint32_t *__restrict__ nbr,
+                                                    uint8_t *__restrict__ out)
+{
+    const Node nd = tile_node(g, t, blockIdx.x);
+    const int any = nd.in && nbr[(uint32_t)nd.x + (uint32_t)g.nx * ((uint32_t)nd.y + (uint32_t)g.ny * (uint32_t)nd.z)] != 0u;
+    const int r = __syncthreads_or(any);
+    if (threadIdx.x == 0) out[blockIdx.x] = r ? 1 : 0;
 }
 
 template <int BX, int BY>
@@ -296,11 +309,11 @@ hipError_t launch_hydro(const Grid &g, const Tiling &t, const DevParams &p, cons
     const bool ntl = t.bx >= g.nx;
 #define CAC_HYDRO(NT_)                                                                                                \
     if (ntl)                                                                                                          \
-        k_hydro<NT_, true><<<t.ntiles, NT_, 0, s>>>(g, t, p, F.f[fcur], F.f[fcur ^ 1], F.phi[pcur], F.nbr, F.u,       \
-                                                    F.flag);                                                          \
+        k_hydro<NT_, true><<<t.ntiles, NT_, 0, s>>>(g, t, p, F.f[fcur], F.f[fcur ^ 1], F.phi[pcur], F.nbr,            \
+                                                    F.twall, F.u, F.flag);                                            \
     else                                                                                                              \
-        k_hydro<NT_, false><<<t.ntiles, NT_, 0, s>>>(g, t, p, F.f[fcur], F.f[fcur ^ 1], F.phi[pcur], F.nbr, F.u,      \
-                                                     F.flag);
+        k_hydro<NT_, false><<<t.ntiles, NT_, 0, s>>>(g, t, p, F.f[fcur], F.f[fcur ^ 1], F.phi[pcur], F.nbr,           \
+                                                     F.twall, F.u, F.flag);
     switch (nt) {
     case 128: CAC_HYDRO(128) break;
     case 256: CAC_HYDRO(256) break;
@@ -308,6 +321,12 @@ hipError_t launch_hydro(const Grid &g, const Tiling &t, const DevParams &p, cons
     default: return hipErrorInvalidValue;
     }
 #undef CAC_HYDRO
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_walls(const Grid &g, const Tiling &t, const Fields &F, hipStream_t s)
+{
+    k_tile_walls<<<t.ntiles, t.bx * t.by * t.bz, 0, s>>>(g, t, F.nbr, F.twall);
     return hipGetLastError();
 }
 

@@ -340,15 +340,17 @@ cac_status cac_init(cac_handle **hp, int nx, int ny, int nz, const cac_params *p
     F.flag = (uint32_t *)dev_alloc(h, 256);
     const size_t nchunk = (Nf + 1023) / 1024;
     F.chunk = (uint8_t *)dev_alloc(h, nchunk);
+    F.twall = (uint8_t *)dev_alloc(h, h->partial_cap);
     if (!F.f[0] || !F.f[1] || !F.phi[0] || !F.phi[1] || !F.u || !F.a || !F.nbr || !F.solid || !F.pstar0 ||
-        !F.partial || !F.scal || !F.flag || !F.chunk) {
+        !F.partial || !F.scal || !F.flag || !F.chunk || !F.twall) {
         for (void *q : h->owned) (void)hipFree(q);
         delete h;
         return CAC_ERR_ALLOC;
     }
     if (hipMemsetAsync(F.flag, 0, 256, h->stream) != hipSuccess ||
         hipMemsetAsync(F.scal, 0, 8 * sizeof(double), h->stream) != hipSuccess ||
-        hipMemsetAsync(F.chunk, 0, nchunk, h->stream) != hipSuccess) {
+        hipMemsetAsync(F.chunk, 0, nchunk, h->stream) != hipSuccess ||
+        hipMemsetAsync(F.twall, 1, h->partial_cap, h->stream) != hipSuccess) {
         for (void *q : h->owned) (void)hipFree(q);
         delete h;
         return CAC_ERR_HIP;
@@ -393,6 +395,7 @@ cac_status cac_set_geometry(cac_handle *h, const uint8_t *solid, const float *th
     h->F.nwall = nb;
     HIPCHK(h, hipMemcpyAsync(h->F.nbr, nbr.data(), N * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->F.solid, solid, N, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, launch_tile_walls(h->g, h->t, h->F, h->stream));
     if (nb) {
         HIPCHK(h, hipMemcpyAsync(h->F.wall_idx, h->widx.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
         HIPCHK(h, hipMemcpyAsync(h->F.wall_q, q.data(), nb, hipMemcpyHostToDevice, h->stream));
@@ -575,6 +578,7 @@ cac_status cac_set_launch(cac_handle *h, int bx, int by, int bz, int phase_tile,
     t.phase = phase_tile;
     if (t.ntiles > h->partial_cap) return fail(h, CAC_ERR_ARG, "too many tiles");
     h->t = t;
+    if (h->geometry) HIPCHK(h, launch_tile_walls(h->g, h->t, h->F, h->stream));
     h->use_graph = use_graph != 0;
     drop_graphs(h);
     return CAC_OK;

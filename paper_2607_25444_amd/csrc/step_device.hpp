@@ -400,12 +400,13 @@ template <bool NTL>
 __device__ __forceinline__ void hydro_node(const Grid &g, const DevParams &p, const Node &nd,
                                            const float *__restrict__ fin, float *__restrict__ fout,
                                            const float *__restrict__ phi, const uint32_t *__restrict__ nbr,
-                                           float *__restrict__ u, uint32_t *__restrict__ flag)
+                                           float *__restrict__ u, uint32_t *__restrict__ flag, bool walls = true)
 {
     if (!nd.in) return;
     const Offs o = node_offsets(g, nd.x, nd.y, nd.z);
     const uint32_t n = at<0, 0, 0>(o);
-    const uint32_t m = nbr[n];
+    // walls == false: the caller knows that no node of its tile is solid or next to a solid node
+    const uint32_t m = walls ? nbr[n] : 0u;
     if (m & 1u) return;
     const uint32_t N = g.N;
 

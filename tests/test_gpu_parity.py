@@ -225,6 +225,27 @@ def test_full_size_one_step(orc, name):
     _cmp(g, o, w, orc, 2e-6, 1e-5, with_f=False)
 
 
+@pytest.mark.parametrize("name", ["spreading", "porous", "impact"])
+def test_full_size_20_steps(orc, name):
+    """The full-size workloads besides the orifice (spreading 256 x 256 x 128,
+    porous packing 256 x 256 x 128, impact 256^3 at density ratio 1000), 20
+    steps in the launch the benchmark uses: phi within 1e-5 and u within 1e-4
+    of its maximum on every fluid node, p* and every ghost as well."""
+    from paper_2607_25444_amd import tuning
+    w = {"spreading": lambda: W.spreading_256(0), "porous": lambda: W.porous_256(0),
+         "impact": lambda: W.impact_256()}[name]()
+    print(f"[full size] {w.name} N={w.N}, 20 steps", flush=True)
+    o = oracle_run(orc, w, 20)
+    g = gpu_run(w, 20, launch=tuning.launch_for(w.shape))
+    fl, wall = _masks(w, orc)
+    N = w.N
+    dphi = np.abs(g["phi"] - o["phi"])
+    uo, ug = o["u"].reshape(3, N)[:, fl], g["u"].reshape(3, N)[:, fl]
+    print("phi err fluid", dphi[fl].max(), "ghost", dphi[wall].max(), "u err", np.abs(ug - uo).max(),
+          "max u", np.abs(uo).max(), flush=True)
+    _cmp(g, o, w, orc, 1e-5, 1e-4, with_f=False)
+
+
 def test_scaled_orifice_200_steps(orc):
     """The orifice workload scaled down (48 x 48 x 96, plate 4 cells thick with
     a hole of diameter 12, droplet R = 10 just above it, the paper's orifice
