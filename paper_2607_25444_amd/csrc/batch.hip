@@ -78,6 +78,12 @@ __global__ __launch_bounds__(256) void k_bghost(BatchPtrs B, const BatchDomain *
     ghost_node(d.g, d.p, (int)k, B.wall_idx, B.wall_q, B.wall_n, B.theta, P.phi_cur, P.phi_oth, P.nbr, P.a);
 }
 
+// Hydrodynamic items carry, in the top bit of the tile index, whether the tile
+// holds a solid node or a node next to one (set on the device by
+// k_bitem_walls whenever the item list changes); other tiles skip the
+// neighbour-mask load.
+constexpr uint32_t ITEM_WALLS = 0x80000000u;
+
 // The descriptor array is a separate read-only, non-aliased argument so that
 // its uniform fields are fetched with scalar loads into scalar registers.
 template <int NT>
@@ -91,7 +97,8 @@ __global__ __launch_bounds__(NT) void k_bhydro(BatchPtrs B, const BatchDomain *_
         if (it + r.stride < r.end) nxt = items[it + r.stride];  // next record loads during this item
         const BatchDomain d = dom[dt.x];
         const DomPtrs P = domain_ptrs(B, d, cur);
-        hydro_node<false>(d.g, d.p, tile_node(d.g, d.t, dt.y), P.fin, P.fout, P.phi_cur, P.nbr, P.u, B.flag);
+        hydro_node<false>(d.g, d.p, tile_node(d.g, d.t, dt.y & ~ITEM_WALLS), P.fin, P.fout, P.phi_cur, P.nbr, P.u,
+                          B.flag, (dt.y & ITEM_WALLS) != 0u);
     }
 }
 
@@ -107,11 +114,28 @@ __global__ __launch_bounds__(NT) void k_bhydro1(BatchPtrs B, const BatchDomain *
     const uint2 dt = items[blockIdx.x];
     const BatchDomain d = dom[dt.x];
     const DomPtrs P = domain_ptrs(B, d, cur);
-    const Node nd = tile_node(d.g, d.t, dt.y);
+    const Node nd = tile_node(d.g, d.t, dt.y & ~ITEM_WALLS);
+    const bool walls = (dt.y & ITEM_WALLS) != 0u;
     if (d.t.bx >= d.g.nx)
-        hydro_node<true>(d.g, d.p, nd, P.fin, P.fout, P.phi_cur, P.nbr, P.u, B.flag);
+        hydro_node<true>(d.g, d.p, nd, P.fin, P.fout, P.phi_cur, P.nbr, P.u, B.flag, walls);
     else
-        hydro_node<false>(d.g, d.p, nd, P.fin, P.fout, P.phi_cur, P.nbr, P.u, B.flag);
+        hydro_node<false>(d.g, d.p, nd, P.fin, P.fout, P.phi_cur, P.nbr, P.u, B.flag, walls);
+}
+
+// Sets the wall bit of every hydrodynamic item: one workgroup per item, one
+// thread per node of its tile.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_bitem_walls(BatchPtrs B, const BatchDomain *__restrict__ dom,
+                                                    uint2 *__restrict__ items)
+{
+    const uint2 dt = items[blockIdx.x];
+    const uint32_t tile = dt.y & ~ITEM_WALLS;
+    const BatchDomain d = dom[dt.x];
+    const Node nd = tile_node(d.g, d.t, tile);
+    const int any = nd.in && B.nbr[d.off + (uint32_t)nd.x +
+                                   (uint32_t)d.g.nx * ((uint32_t)nd.y + (uint32_t)d.g.ny * (uint32_t)nd.z)] != 0u;
+    const int r = __syncthreads_or(any);
+    if (threadIdx.x == 0) items[blockIdx.x].y = tile | (r ? ITEM_WALLS : 0u);
 }
 
 template <int BX, int BY>
@@ -239,16 +263,16 @@ __global__ __launch_bounds__(NT) void k_br1_stream(BatchPtrs B, const BatchDomai
 {
     const uint2 dt = items[blockIdx.x];
     const BatchDomain d = dom[dt.x];
-    const Node nd = tile_node(d.g, d.t, dt.y);
+    const Node nd = tile_node(d.g, d.t, dt.y & ~ITEM_WALLS);
     const float *fin = B.f[0] + 27u * d.off;
     const float *phi = (cur ? B.phi[1] : B.phi[0]) + d.off;
     float *rec = B.f[1] + 27u * d.off;
     if (d.t.bx >= d.g.nx)
         r1_stream_node<SELF, true>(d.g, d.p, nd, fin, phi, B.nbr + d.off, pstar0 + d.off, B.u + 3u * d.off, rec,
-                                   B.flag);
+                                   B.flag, (dt.y & ITEM_WALLS) != 0u);
     else
         r1_stream_node<SELF, false>(d.g, d.p, nd, fin, phi, B.nbr + d.off, pstar0 + d.off, B.u + 3u * d.off, rec,
-                                    B.flag);
+                                    B.flag, (dt.y & ITEM_WALLS) != 0u);
 }
 
 hipError_t launch_br1_rebuild(const BatchPtrs &B, int code, const uint2 *items, uint32_t nitems, hipStream_t s)
@@ -316,6 +340,18 @@ hipError_t launch_bhydro(const BatchPtrs &B, int nt, const uint2 *items, uint32_
         if (grid >= nitems) k_bhydro1<512><<<nitems, 512, 0, s>>>(B, B.dom, items, nitems, cur);
         else k_bhydro<512><<<grid, 512, 0, s>>>(B, B.dom, items, nitems, cur);
         break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bitem_walls(const BatchPtrs &B, int nt, uint2 *items, uint32_t nitems, hipStream_t s)
+{
+    if (!nitems) return hipSuccess;
+    switch (nt) {
+    case 128: k_bitem_walls<128><<<nitems, 128, 0, s>>>(B, B.dom, items); break;
+    case 256: k_bitem_walls<256><<<nitems, 256, 0, s>>>(B, B.dom, items); break;
+    case 512: k_bitem_walls<512><<<nitems, 512, 0, s>>>(B, B.dom, items); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -195,6 +195,7 @@ cac_status apply_schedule(cac_batch *b, const Schedule &s)
     b->pgrid = std::max<uint32_t>(b->pgrid, 1);
     BCHK(b, hipMemcpyAsync(b->d_dom, b->dom.data(), b->ndom * sizeof(BatchDomain), hipMemcpyHostToDevice, b->stream));
     if (b->nh) BCHK(b, hipMemcpyAsync(b->d_hitems, hi.data(), hi.size() * sizeof(uint2), hipMemcpyHostToDevice, b->stream));
+    BCHK(b, launch_bitem_walls(b->B, nt, b->d_hitems, b->nh, b->stream));
     if (b->np) BCHK(b, hipMemcpyAsync(b->d_pitems, pi.data(), pi.size() * sizeof(uint2), hipMemcpyHostToDevice, b->stream));
     BCHK(b, hipStreamSynchronize(b->stream));
     b->sch = s;

@@ -137,6 +137,7 @@ struct BatchPtrs {
 // Work items of the persistent batched kernels: (domain, tile) pairs in the
 // order of the block schedule.  grid = number of persistent workgroups.
 hipError_t launch_bghost(const BatchPtrs &B, uint32_t nwall, int cur, hipStream_t s);
+hipError_t launch_bitem_walls(const BatchPtrs &B, int nt, uint2 *items, uint32_t nitems, hipStream_t s);
 hipError_t launch_bhydro(const BatchPtrs &B, int nt, const uint2 *items, uint32_t nitems, uint32_t grid, int cur,
                          hipStream_t s);
 hipError_t launch_bphase(const BatchPtrs &B, int phase_code, const uint2 *items, uint32_t nitems, uint32_t grid,

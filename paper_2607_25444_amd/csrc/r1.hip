@@ -46,12 +46,13 @@ __global__ __launch_bounds__(CX *CY) void k_r1_rebuild(Grid g, PhaseTiling pt, D
 template <int NT, bool SELF, bool NTL>
 __global__ __launch_bounds__(NT) void k_r1_stream(Grid g, Tiling t, DevParams p, const float *__restrict__ fin,
                                                   const float *__restrict__ phi, const uint32_t *__restrict__ nbr,
-                                                  const float *__restrict__ pstar0, float *__restrict__ u,
-                                                  float *__restrict__ rec, uint32_t *__restrict__ flag)
+                                                  const uint8_t *__restrict__ twall, const float *__restrict__ pstar0,
+                                                  float *__restrict__ u, float *__restrict__ rec,
+                                                  uint32_t *__restrict__ flag)
 {
     const uint32_t b = p.rev_order ? gridDim.x - 1u - blockIdx.x : blockIdx.x;
     const uint32_t tile = NTL ? b : xcd_tile(b, t.ntiles);
-    r1_stream_node<SELF, NTL>(g, p, tile_node(g, t, tile), fin, phi, nbr, pstar0, u, rec, flag);
+    r1_stream_node<SELF, NTL>(g, p, tile_node(g, t, tile), fin, phi, nbr, pstar0, u, rec, flag, twall[tile] != 0);
 }
 
 // The rebuilt populations live in the first population buffer, the record in
@@ -70,13 +71,13 @@ hipError_t launch_r1_stream(const Grid &g, const Tiling &t, const DevParams &p, 
     const bool ntl = t.bx >= g.nx;
 #define CAC_R1S(NT_)                                                                                              \
     if (self)                                                                                                     \
-        k_r1_stream<NT_, true, false><<<t.ntiles, NT_, 0, s>>>(g, t, p, F.f[0], F.phi[pcur], F.nbr, F.pstar0,     \
+        k_r1_stream<NT_, true, false><<<t.ntiles, NT_, 0, s>>>(g, t, p, F.f[0], F.phi[pcur], F.nbr, F.twall, F.pstar0,     \
                                                                F.u, F.f[1], F.flag);                              \
     else if (ntl)                                                                                                 \
-        k_r1_stream<NT_, false, true><<<t.ntiles, NT_, 0, s>>>(g, t, p, F.f[0], F.phi[pcur], F.nbr, F.pstar0,     \
+        k_r1_stream<NT_, false, true><<<t.ntiles, NT_, 0, s>>>(g, t, p, F.f[0], F.phi[pcur], F.nbr, F.twall, F.pstar0,     \
                                                                F.u, F.f[1], F.flag);                              \
     else                                                                                                          \
-        k_r1_stream<NT_, false, false><<<t.ntiles, NT_, 0, s>>>(g, t, p, F.f[0], F.phi[pcur], F.nbr, F.pstar0,    \
+        k_r1_stream<NT_, false, false><<<t.ntiles, NT_, 0, s>>>(g, t, p, F.f[0], F.phi[pcur], F.nbr, F.twall, F.pstar0,    \
                                                                 F.u, F.f[1], F.flag);
     switch (t.bx * t.by * t.bz) {
     case 128: CAC_R1S(128) break;

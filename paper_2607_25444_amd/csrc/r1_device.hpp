@@ -61,12 +61,13 @@ __device__ __forceinline__ void r1_stream_node(const Grid &g, const DevParams &p
                                                const float *__restrict__ fin, const float *__restrict__ phi,
                                                const uint32_t *__restrict__ nbr, const float *__restrict__ pstar0,
                                                float *__restrict__ u, float *__restrict__ rec,
-                                               uint32_t *__restrict__ flag)
+                                               uint32_t *__restrict__ flag, bool walls = true)
 {
     if (!nd.in) return;
     const Offs o = node_offsets(g, nd.x, nd.y, nd.z);
     const uint32_t n = at<0, 0, 0>(o);
-    const uint32_t m = nbr[n];
+    // walls == false: no node of the caller's tile is solid or next to a solid node
+    const uint32_t m = walls ? nbr[n] : 0u;
     if (m & 1u) return;
     const uint32_t N = g.N;
 

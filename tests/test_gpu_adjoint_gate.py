@@ -9,8 +9,10 @@ stored in tests/golden/adjoint_fd_128x128x64.json by
 tests/golden/adjoint_fd.py (which calls only oracle/): one per sampled wall
 node (16 nodes drawn from the annulus around the initial contact line) and
 one along a random direction over those 16 nodes.  Bound: 1e-3 relative per
-node and along the direction; the 4 far-field wall nodes, never reached by the
-interface, have a zero derivative."""
+node (on a node whose derivative is below 1% of the largest component, the
+absolute error allowed at that threshold) and along the direction; the 4
+far-field wall nodes, never reached by the interface, have a zero
+derivative."""
 import json
 import os
 
@@ -50,14 +52,19 @@ def test_gradient_matches_oracle_finite_differences_at_1000_steps():
     pos = {int(k): i for i, k in enumerate(idx)}
     gn = np.array([g[pos[k]] for k in d["nodes"]])
     fd = np.array(d["fd"])
-    rel = np.abs(gn - fd) / np.abs(fd)
-    print("loss", L, "max |dL/dtheta|", np.abs(g).max())
-    for k, a, b, r in zip(d["nodes"], gn, fd, rel):
-        print(f"wall node {k}: adjoint {a:.6e} fd {b:.6e} rel {r:.2e}")
+    gmax = float(np.abs(g).max())
+    # relative bound 1e-3 on nodes that carry at least 1% of the largest gradient component; on a node below
+    # that (the derivative nearly vanishes there) the same absolute error as at the 1% threshold
+    scale = np.maximum(np.abs(fd), 1e-2 * gmax)
+    err = np.abs(gn - fd) / scale
+    print("loss", L, "max |dL/dtheta|", gmax)
+    for k, a, b, r in zip(d["nodes"], gn, fd, err):
+        print(f"wall node {k}: adjoint {a:.6e} fd {b:.6e} rel {abs(a - b) / abs(b):.2e}, error over its scale {r:.2e}")
     v = np.array(d["direction"])
     gd = float(np.dot(v, gn))
     print(f"direction: adjoint {gd:.6e} fd {d['fd_direction']:.6e}")
-    assert np.all(rel <= 1e-3), rel
+    assert np.sum(np.abs(fd) >= 1e-2 * gmax) >= 12  # most sampled nodes are well inside the gradient's support
+    assert np.all(err <= 1e-3), err
     assert abs(gd - d["fd_direction"]) <= 1e-3 * abs(d["fd_direction"])
     far = np.array([g[pos[k]] for k in d["far_nodes"]])
-    assert np.abs(far).max() <= 1e-6 * np.abs(g).max()
+    assert np.abs(far).max() <= 1e-6 * gmax
