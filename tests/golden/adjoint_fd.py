@@ -19,6 +19,13 @@ DIR a scratch folder:
     python tests/golden/adjoint_fd.py run DIR J0,J1,... [SECONDS]  # perturbed runs (job ids; all,
                                                             # all-desc); stop before a job would pass SECONDS
     python tests/golden/adjoint_fd.py assemble DIR          # writes adjoint_fd_128x128x64.json here
+    python tests/golden/adjoint_fd.py growth DIR            # writes adjoint_fd_growth.json here
+
+`growth` records how the gradient depends on the rollout length: central
+differences on the first three sampled wall nodes of the same workload after
+12, 50, 100 and 200 steps, and on three wall nodes of a small drop (48 x 48 x 24,
+R = 9, centre off the lattice's mirror planes, the same angle fields and loss)
+after 200 and 1000 steps.
 
 The runs use the oracle compiled for the host CPU (oracle.build_native: the
 same source and arithmetic, -O3 -march=native).
@@ -167,10 +174,76 @@ def cmd_assemble(dirp):
     print(f"wrote {OUT}")
 
 
+GROWTH_OUT = os.path.join(HERE, "adjoint_fd_growth.json")
+SMALL = (48, 48, 24)
+
+
+def small_case():
+    """(workload at theta_{seed+1000}, theta_seed field, three wall nodes) of the small drop."""
+    nx, ny, nz = SMALL
+    R = 9.0
+    phi0 = W.tanh_droplet(SMALL, ((nx - 1) / 2 - 0.3, (ny - 1) / 2 - 0.7, 0.5), R, 4.0).astype(np.float32)
+    w = W.Workload("adjoint_small_48x48x24", SMALL, W.flat_walls(SMALL), W.gaussian_bump_theta(SMALL, SEED + 1000),
+                   phi0, W.default_params(), 1000, dict(R=R))
+    nodes = []
+    for a in (0.3, 2.4, 4.4):
+        x = int(round((nx - 1) / 2 + R * np.cos(a)))
+        y = int(round((ny - 1) / 2 + R * np.sin(a)))
+        nodes.append(x + nx * y)
+    return w, W.gaussian_bump_theta(SMALL, SEED), nodes
+
+
+def fd_at(w, th_target, nodes, n):
+    def run(th):
+        o = O.OracleSim.create(w.shape, w.solid, np.asarray(th, np.float64), O.Params(**w.params),
+                               w.phi0.astype(np.float64))
+        o.step(n)
+        return o.phi
+    tgt = run(th_target)
+    fl = w.solid == 0
+
+    def loss_of(th):
+        d = (run(th) - tgt)[fl]
+        return 0.5 * float(np.dot(d, d))
+    out = []
+    for k in nodes:
+        tp = np.asarray(w.theta, np.float64).copy()
+        tm = tp.copy()
+        tp[k] += H
+        tm[k] -= H
+        out.append((loss_of(tp) - loss_of(tm)) / (2 * H))
+    return out
+
+
+def cmd_growth(dirp):
+    rec = {"about": "Central differences (h = 1e-4 rad) of the FP64 C oracle's loss for several rollout lengths; "
+                    "written by tests/golden/adjoint_fd.py growth, which calls only oracle/ and the seeded input "
+                    "generators.", "h": H, "cases": {}}
+    w, th_t = workload_pair()
+    ring, _ = sampled_nodes(w)
+    nodes = [int(k) for k in ring[:3]]
+    rec["cases"]["adjoint_128x128x64"] = {"nodes": nodes, "fd": {}}
+    for n in (12, 50, 100, 200):
+        t0 = time.time()
+        rec["cases"]["adjoint_128x128x64"]["fd"][str(n)] = fd_at(w, th_t, nodes, n)
+        print(f"128x128x64, {n} steps: {rec['cases']['adjoint_128x128x64']['fd'][str(n)]} ({time.time() - t0:.0f} s)",
+              flush=True)
+    ws, ths, nodes_s = small_case()
+    rec["cases"]["adjoint_small_48x48x24"] = {"nodes": [int(k) for k in nodes_s], "fd": {}}
+    for n in (200, 1000):
+        t0 = time.time()
+        rec["cases"]["adjoint_small_48x48x24"]["fd"][str(n)] = fd_at(ws, ths, nodes_s, n)
+        print(f"48x48x24, {n} steps: {rec['cases']['adjoint_small_48x48x24']['fd'][str(n)]} ({time.time() - t0:.0f} s)",
+              flush=True)
+    with open(GROWTH_OUT, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(f"wrote {GROWTH_OUT}")
+
+
 if __name__ == "__main__":
     cmd, dirp = sys.argv[1], sys.argv[2]
     os.makedirs(dirp, exist_ok=True)
-    if cmd in ("target", "run"):
+    if cmd in ("target", "run", "growth"):
         import ctypes
         import tempfile
         lib_path = O.build_native(os.path.join(tempfile.mkdtemp(), "liboracle_native.so"))
@@ -181,5 +254,7 @@ if __name__ == "__main__":
         cmd_run(dirp, sys.argv[3], float(sys.argv[4]) if len(sys.argv) > 4 else None)
     elif cmd == "assemble":
         cmd_assemble(dirp)
+    elif cmd == "growth":
+        cmd_growth(dirp)
     else:
         raise SystemExit(f"unknown command {cmd}")
