@@ -105,18 +105,30 @@ __global__ __launch_bounds__(256) void k_poison(Grid g, const uint32_t *__restri
 
 // ------------------------------------------------------------------ V: volume
 
-// Sum of the per-tile partials in a fixed order (deterministic), then
-// lambda = (M_target - M*) / W when W > 0 (Eqs. (49)-(55)).
-__global__ __launch_bounds__(1024) void k_vol_finalize(const double2 *__restrict__ partial, uint32_t np,
-                                                       double *__restrict__ scal, int vc)
+// Sum of the per-tile partials (sum phi*, sum chi) over np tiles in a fixed
+// order, for a 256-thread workgroup: thread t adds tiles t, t + 256, ...,
+// then the workgroup tree of block_sum2.  Every kernel that forms lambda
+// uses it, so lambda is bitwise the same wherever it is formed (the in-place
+// correction of the step and the out-of-place one of the adjoint's replay).
+// Thread 0 receives the sums.
+__device__ __forceinline__ void tile_sums(const double2 *__restrict__ partial, uint32_t np, double &x, double &y)
 {
-    double x = 0.0, y = 0.0;
-    for (uint32_t k = threadIdx.x; k < np; k += 1024) {
+    x = 0.0;
+    y = 0.0;
+    for (uint32_t k = threadIdx.x; k < np; k += 256u) {
         const double2 v = partial[k];
         x += v.x;
         y += v.y;
     }
-    block_sum2<1024>(x, y);
+    block_sum2<256>(x, y);
+}
+
+// lambda = (M_target - M*) / W when W > 0 (Eqs. (49)-(55)).
+__global__ __launch_bounds__(256) void k_vol_finalize(const double2 *__restrict__ partial, uint32_t np,
+                                                      double *__restrict__ scal, int vc)
+{
+    double x, y;
+    tile_sums(partial, np, x, y);
     if (threadIdx.x == 0) {
         const double lam = (vc && y > 0.0) ? (scal[0] - x) / y : 0.0;
         scal[1] = lam;
@@ -127,9 +139,9 @@ __global__ __launch_bounds__(1024) void k_vol_finalize(const double2 *__restrict
 
 // The volume correction in one pass.  Each workgroup covers 1024 nodes (four
 // per thread).  lambda = (M_target - M*) / W when W > 0 (Eqs. (49)-(55)),
-// from the per-tile partials summed in a fixed order: every workgroup that
-// needs it forms the same sum itself, so no second launch orders a finalize
-// before the update; workgroup 0 stores lambda, M* and W.  Then
+// from the per-tile partials summed in a fixed order (tile_sums): every
+// workgroup that needs it forms the same sum itself, so no second launch
+// orders a finalize before the update; workgroup 0 stores lambda, M* and W.  Then
 // phi^{n+1} = phi* + lambda chi(phi*) on the interface fluid nodes (Eq. (53)).
 // A workgroup whose chunk byte is clear holds no interface node (the phase
 // update sets the byte of every node it counts in W) and returns at once; a
@@ -164,13 +176,8 @@ __global__ __launch_bounds__(256) void k_vol_apply(uint32_t N, const uint8_t *__
                 v[k] = phi[n0 + k];
             }
     }
-    double x = 0.0, y = 0.0;
-    for (uint32_t k = threadIdx.x; k < np; k += 256u) {
-        const double2 pk = partial[k];
-        x += pk.x;
-        y += pk.y;
-    }
-    block_sum2<256>(x, y);
+    double x, y;
+    tile_sums(partial, np, x, y);
     __shared__ double slam;
     if (threadIdx.x == 0) {
         const double l = (vc && y > 0.0) ? (scal[0] - x) / y : 0.0;
@@ -436,7 +443,7 @@ hipError_t launch_volume(const Grid &g, const Tiling &t, const DevParams &p, con
 hipError_t launch_volume_copy(const Grid &g, const Tiling &t, const DevParams &p, const Fields &F,
                               const float *phistar, const float *phihat, float *out, hipStream_t s)
 {
-    k_vol_finalize<<<1, 1024, 0, s>>>(F.partial, phase_tiles(g, t), F.scal, p.volume_correction);
+    k_vol_finalize<<<1, 256, 0, s>>>(F.partial, phase_tiles(g, t), F.scal, p.volume_correction);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_vol_copy<<<blocks_for(g.N, 256), 256, 0, s>>>(g.N, F.solid, phistar, phihat, out, F.scal, p.eps_phi);
