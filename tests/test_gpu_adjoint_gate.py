@@ -15,8 +15,9 @@ far-field wall nodes, never reached by the interface, have a zero
 derivative.
 
 Measured: the FP32 reverse sweep misses that bound at 1000 steps by two orders
-of magnitude on this drop.  Its error grows exponentially with the rollout
-length (test_error_growth_large_drop); on a drop small enough that FP32
+of magnitude on this drop.  Its error grows with the rollout
+length (test_error_growth_large_drop: 1e-6 after 12 steps, 1e-3 after
+100-200, a blow-up between 500 and 1000); on a drop small enough that FP32
 resolves its whole liquid phase the same code agrees with central differences
 at 1000 steps (test_small_drop_1000_steps).  The cause: where 1 - phi is below
 2^-24 (the inside of the R = 24 drop), the FP32 phase field is flat to within
@@ -38,7 +39,7 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "adj
 
 
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="finite-difference reference not generated yet")
-@pytest.mark.xfail(strict=True, reason="FP32 reverse sweep: error grows exponentially on the R = 24 drop, whose "
+@pytest.mark.xfail(strict=True, reason="FP32 reverse sweep: the error grows with the rollout on the R = 24 drop, whose "
                                        "liquid phase FP32 cannot resolve (measured 1e2 relative at 1000 steps)")
 def test_gradient_matches_oracle_finite_differences_at_1000_steps():
     from paper_2607_25444_amd import capi, tuning
@@ -116,7 +117,9 @@ def _err(gn, fd):
 def test_error_growth_large_drop():
     """The 128 x 128 x 64 workload after 12 to 200 steps (K = 50) against central
     differences of the FP64 oracle on three sampled wall nodes: agreement to
-    1e-5 after 12 steps and 1e-3 after 50; the error then keeps growing."""
+    1e-5 after 12 steps and 1e-3 after 50, then errors of about 1e-3 after 100
+    and 200 steps (bound 1e-2); the gradient blows up between 500 and 1000
+    steps (the expected failure above)."""
     d = json.load(open(GROWTH))["cases"]["adjoint_128x128x64"]
     w = W.adjoint_128(seed=1000)
     theta_t = W.adjoint_128(seed=0).theta
@@ -127,8 +130,7 @@ def test_error_growth_large_drop():
         print(f"{n} steps: adjoint {gn} fd {fd} error {errs[int(n)]:.2e}", flush=True)
     assert errs[12] <= 1e-5
     assert errs[50] <= 1e-3
-    steps = sorted(errs)
-    assert all(errs[a] < errs[b] for a, b in zip(steps, steps[1:]))  # grows with the rollout length
+    assert max(errs.values()) <= 1e-2
 
 
 @pytest.mark.skipif(not os.path.exists(GROWTH), reason="finite-difference reference not generated yet")
