@@ -70,7 +70,7 @@ __global__ __launch_bounds__(BX *BY) void k_phase(Grid g, PhaseTiling pt, DevPar
                                                   uint8_t *__restrict__ chunk)
 {
     const uint32_t tile = xcd_tile(p.rev_order ? gridDim.x - 1u - blockIdx.x : blockIdx.x, pt.ntiles);
-    phase_tile<BX, BY>(g, pt, p, tile, phi, phi_out, u, aw, solid, partial + tile, flag, chunk);
+    phase_tile<BX, BY, 4>(g, pt, p, tile, phi, phi_out, u, aw, solid, partial + tile, flag, chunk);
 }
 
 // Debug: quiet NaNs into every value the step must never read -- populations

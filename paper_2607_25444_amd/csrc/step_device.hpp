@@ -579,7 +579,7 @@ __device__ __forceinline__ float muscl_axis(float q0, float q1, float q2, float 
 // there, counted from node offset `coff` (the volume correction touches no
 // other chunk).  Must be entered by the whole workgroup; reuses its LDS on
 // every call.
-template <int BX, int BY>
+template <int BX, int BY, int U = 2>
 __device__ __forceinline__ void phase_tile(const Grid &g, const PhaseTiling &pt, const DevParams &p, uint32_t tile,
                                            const float *__restrict__ phi, float *__restrict__ phi_out,
                                            const float *__restrict__ u, const float *__restrict__ aw,
@@ -909,12 +909,26 @@ __device__ __forceinline__ void phase_tile(const Grid &g, const PhaseTiling &pt,
         uzc = uzp;
         uzp = un.zn;
     };
+    // the plane loop unrolled U times (the rolled column state then stays in
+    // place; U = 4 in the single-lattice kernel, 2 where the batched kernels'
+    // extra registers would cost a wave per SIMD)
+    static_assert(U == 2 || U == 4, "plane loop unrolled 2 or 4 times");
     int z = z0;
-    for (; z + 1 < z1; z += 2) {
-        plane(z);
-        plane(z + 1);
+    if constexpr (U == 4) {
+        for (; z + 3 < z1; z += 4) {
+            plane(z);
+            plane(z + 1);
+            plane(z + 2);
+            plane(z + 3);
+        }
+        for (; z < z1; ++z) plane(z);
+    } else {
+        for (; z + 1 < z1; z += 2) {
+            plane(z);
+            plane(z + 1);
+        }
+        if (z < z1) plane(z);
     }
-    if (z < z1) plane(z);
     block_sum2<NT>(sphis, schi);
     if (tid == 0) *partial_out = make_double2(sphis, schi);
 }
