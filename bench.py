@@ -57,17 +57,18 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload_name):
-    """HBM bytes per hydro launch from the committed rocprofv3 counter summary
-    for this workload, if there is one and it was taken on the current kernel
-    source; else None."""
+def measured_traffic(workload_name, key="bytes_per_launch"):
+    """HBM bytes per hydro launch (key "bytes_per_launch") or per whole step
+    (key "step_bytes") from the committed rocprofv3 counter summary for this
+    workload, if there is one and it was taken on the current kernel source;
+    else None."""
     p = os.path.join(ROOT, "profiles", f"hydro_traffic_{workload_name}.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
     if d.get("workload") != workload_name or d.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return d.get("bytes_per_launch")
+    return d.get(key)
 
 
 def host_cpu_model():
@@ -181,6 +182,12 @@ def plain_block(torch, capi, w, launch, steps, warmup, probes):
             "volume_rel_drift": (M1 - M0) / M0,
         },
     }
+    # measured HBM bytes of the whole step (W, H, P and V, rocprofv3 FETCH_SIZE + WRITE_SIZE), when the committed
+    # counters match the kernel source
+    sbytes = measured_traffic(w.name, "step_bytes")
+    out["step"]["measured_bytes_per_step"] = sbytes
+    out["step"]["measured_GBs"] = round(sbytes / (ms_step * 1e-3) / 1e9, 1) if sbytes else None
+    out["step"]["measured_frac_of_peak"] = round(sbytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if sbytes else None
     if probes:
         # achievable ceilings, measured live after the timed region: the
         # collide-stream's memory access pattern without its arithmetic (27-plane
