@@ -1,7 +1,8 @@
 """Launch shapes of the bulk kernels (tile bx * by * bz nodes per workgroup).
 
 ``launch_for`` is the configuration the benchmark times and the full-size
-parity test uses; the autotuner in ``bench.py --tune`` searches the same space.
+parity test uses; ``CANDIDATES`` are the hydrodynamic tiles that sweeps of it
+cover (``bench.py --launch bx,by,bz,graph,phase`` times one of them).
 """
 from __future__ import annotations
 
@@ -22,8 +23,11 @@ def launch_for(shape):
     workgroup order (0.354 vs 0.397 ms on 256 x 256 x 128; 12.3 vs 11.8 GLUPS
     for the plain step on 128 x 128 x 64).  Other widths take the widest of
     256, 128, 64, 32, 16 that divides nx (no half-empty tile at the row end)
-    with ordinary loads; a 512-wide row-wide tile was measured slower than
-    256 x 2 (16.6 vs 17.7 GLUPS on 512^3)."""
+    with ordinary loads, 64-wide ones in 64 x 8 tiles (the collide-stream on
+    the 192 x 192 x 768 orifice lattice: 1.312 ms against 1.326 ms in 64 x 4,
+    1.313 in 64 x 4 x 2, 1.325 in 64 x 2, 1.39-1.40 ms in 32-wide tiles); a
+    512-wide row-wide tile was measured slower than 256 x 2 (16.6 vs 17.7 GLUPS
+    on 512^3)."""
     nx, ny, nz = shape
     n = nx * ny * nz
     if nx in (128, 256):
@@ -33,6 +37,8 @@ def launch_for(shape):
         bx = div[0] if div else (64 if nx >= 64 else (32 if nx >= 32 else 16))
         if bx >= 128:
             by, bz = 512 // bx, 1
+        elif bx == 64:
+            by, bz = 8, 1
         else:
             by = max(1, min(4, 256 // bx))
             bz = 256 // (bx * by)

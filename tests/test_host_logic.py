@@ -25,7 +25,7 @@ def test_launch_for_sizes_and_shapes():
             if div:
                 assert bx == div[0], (nx, bx)
     assert tuning.launch_for((512, 512, 512))[:3] == (256, 2, 1)
-    assert tuning.launch_for((192, 192, 768))[:3] == (64, 4, 1)
+    assert tuning.launch_for((192, 192, 768))[:3] == (64, 8, 1)
     assert tuning.launch_for((96, 96, 96))[:3] == (32, 4, 2)
     assert tuning.launch_for((128, 128, 256))[3] == 1  # 2^22 nodes
     assert tuning.launch_for((128, 128, 257))[3] == 0
