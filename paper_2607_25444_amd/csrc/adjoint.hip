@@ -1,9 +1,10 @@
 // adjoint.hip -- gfx950 kernels of the reverse (adjoint) step.
 //
 // One reverse step at the recorded forward state of step n:
-//   k_adj_vsum, k_adj_vfin   FP64 sums sum(pb chi), sum(phi*), sum(chi) of the
-//                            volume correction's transpose -> lambda, cbar
-//   k_adj_psi                psi = cotangent of phi* (fluid nodes)
+//   k_adj_vsum               FP64 sums sum(pb chi), sum(phi*), sum(chi) of the
+//                            volume correction's transpose
+//   k_adj_psi                lambda, cbar from those sums; psi = cotangent of
+//                            phi* (fluid nodes)
 //   k_adj_main               per node: transposes of V, P and the collision;
 //                            the transpose of the pull streaming is a gather
 //                            of the neighbours' moment cotangents
@@ -91,30 +92,41 @@ __global__ __launch_bounds__(256) void k_adj_vsum(uint32_t N, const uint8_t *__r
     }
 }
 
-// lambda = (M_target - sum phi*) / W and cbar = sum(pb chi) / W, zero when W = 0
-// or the correction is off; partials added in a fixed order.
-__global__ __launch_bounds__(1024) void k_adj_vfin(const double *__restrict__ red, uint32_t np,
-                                                   const double *__restrict__ scal, double *__restrict__ rs, int vc)
+// psi, the cotangent of phi* on fluid nodes (0 on solid nodes), with
+// lambda = (M_target - sum phi*) / W and cbar = sum(pb chi) / W (zero when
+// W = 0 or the correction is off).  Every workgroup sums the np partials of
+// k_adj_vsum itself, in the same fixed order, so that no separate launch has
+// to finish the sums first; workgroup 0 records lambda and cbar and adds cbar
+// to dL/dM_target (summed over the steps: lambda grows by 1/W per unit of M).
+// ADJ_VSUM_PER_THREAD nodes per thread, in k_adj_vsum's order.
+__global__ __launch_bounds__(256) void k_adj_psi(uint32_t N, DevParams p, AdjStep S, uint32_t np)
 {
     double a = 0.0, b = 0.0, c = 0.0;
-    for (uint32_t k = threadIdx.x; k < np; k += 1024) {
-        a += red[3 * k];
-        b += red[3 * k + 1];
-        c += red[3 * k + 2];
+    for (uint32_t k = threadIdx.x; k < np; k += 256u) {
+        a += S.red[3 * k];
+        b += S.red[3 * k + 1];
+        c += S.red[3 * k + 2];
     }
-    block_sum3<1024>(a, b, c);
+    block_sum3<256>(a, b, c);
+    __shared__ float slc[2];
     if (threadIdx.x == 0) {
-        const bool on = vc && c > 0.0;
-        rs[0] = on ? (scal[0] - b) / c : 0.0;
-        rs[1] = on ? a / c : 0.0;
-        rs[3] += rs[1];  // dL/dM_target summed over the steps (lambda grows by 1/W per unit of M)
+        const bool on = p.volume_correction && c > 0.0;
+        const double lam = on ? (S.scal[0] - b) / c : 0.0, cb = on ? a / c : 0.0;
+        slc[0] = (float)lam;
+        slc[1] = (float)cb;
+        if (blockIdx.x == 0) {
+            S.rs[0] = lam;
+            S.rs[1] = cb;
+            S.rs[3] += cb;
+        }
     }
-}
-
-__global__ __launch_bounds__(256) void k_adj_psi(uint32_t N, DevParams p, AdjStep S)
-{
-    const uint32_t n = blockIdx.x * 256u + threadIdx.x;
-    if (n < N) adj_psi_node(p, S, n);
+    __syncthreads();
+    const float lam = slc[0], cb = slc[1];
+#pragma unroll
+    for (uint32_t r = 0; r < ADJ_VSUM_PER_THREAD; ++r) {
+        const uint32_t n = (blockIdx.x * ADJ_VSUM_PER_THREAD + r) * 256u + threadIdx.x;
+        if (n < N) S.psi[n] = S.solid[n] ? 0.0f : psi_of(S.pb_in[n], S.phistar[n], lam, cb, p.eps_phi);
+    }
 }
 
 // Add the target-volume path to dL/dphi0: M_target is the fluid sum of phi0.
@@ -277,10 +289,7 @@ hipError_t launch_adj_vsum(const Grid &g, const DevParams &p, const AdjStep &S, 
     k_adj_vsum<<<nr, 256, 0, s>>>(g.N, S.solid, S.pb_in, S.phistar, p.eps_phi, S.red);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_adj_vfin<<<1, 1024, 0, s>>>(S.red, nr, S.scal, S.rs, p.volume_correction);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_adj_psi<<<nblocks(g.N, 256), 256, 0, s>>>(g.N, p, S);
+    k_adj_psi<<<nr, 256, 0, s>>>(g.N, p, S, nr);
     return hipGetLastError();
 }
 
