@@ -230,10 +230,10 @@ def copy_probe(torch, nbytes=1 << 30, reps=20, quiet=False):
 
 
 def bench_batch(torch, capi, W, steps, warmup, seed, singles=True, tune_cache=None):
-    from paper_2607_25444_amd import tuning
-
     """Batched persistent step over 64 droplet domains (edges from {32,48,64,96,128},
     R = L/4, angle in [30, 150]); autotuned schedule, graph replay."""
+    from paper_2607_25444_amd import tuning
+
     ws = W.batch_domains(seed)
     t0 = time.perf_counter()
     b = capi.Batch(ws)
