@@ -73,6 +73,7 @@ struct Tiling {
     int tx, ty, tz;   // tiles per axis
     uint32_t ntiles;  // tx*ty*tz
     int phase;        // column tile code of the phase kernel (0 = automatic)
+    uint32_t hyd_lds; // LDS bytes each collide-stream workgroup reserves (unused) to hold it at 4 waves per SIMD
 };
 
 // Column tiling of the phase kernel: ntx x nty column tiles, z-chunks of zc planes.

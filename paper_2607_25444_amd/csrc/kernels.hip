@@ -316,10 +316,10 @@ hipError_t launch_hydro(const Grid &g, const Tiling &t, const DevParams &p, cons
     const bool ntl = t.bx >= g.nx;
 #define CAC_HYDRO(NT_)                                                                                                \
     if (ntl)                                                                                                          \
-        k_hydro<NT_, true><<<t.ntiles, NT_, 0, s>>>(g, t, p, F.f[fcur], F.f[fcur ^ 1], F.phi[pcur], F.nbr,            \
+        k_hydro<NT_, true><<<t.ntiles, NT_, t.hyd_lds, s>>>(g, t, p, F.f[fcur], F.f[fcur ^ 1], F.phi[pcur], F.nbr,            \
                                                     F.twall, F.u, F.flag);                                            \
     else                                                                                                              \
-        k_hydro<NT_, false><<<t.ntiles, NT_, 0, s>>>(g, t, p, F.f[fcur], F.f[fcur ^ 1], F.phi[pcur], F.nbr,           \
+        k_hydro<NT_, false><<<t.ntiles, NT_, t.hyd_lds, s>>>(g, t, p, F.f[fcur], F.f[fcur ^ 1], F.phi[pcur], F.nbr,           \
                                                      F.twall, F.u, F.flag);
     switch (nt) {
     case 128: CAC_HYDRO(128) break;

@@ -37,9 +37,9 @@ hipError_t launch_pull_copy(const Grid &g, const Tiling &t, const float *fin, fl
     const bool ntl = t.bx >= g.nx;
 #define CAC_COPY(NT_)                                                                   \
     if (ntl)                                                                            \
-        k_pull_copy<NT_, true><<<t.ntiles, NT_, 0, s>>>(g, t, fin, fout);               \
+        k_pull_copy<NT_, true><<<t.ntiles, NT_, t.hyd_lds, s>>>(g, t, fin, fout);               \
     else                                                                                \
-        k_pull_copy<NT_, false><<<t.ntiles, NT_, 0, s>>>(g, t, fin, fout);
+        k_pull_copy<NT_, false><<<t.ntiles, NT_, t.hyd_lds, s>>>(g, t, fin, fout);
     switch (nt) {
     case 128: CAC_COPY(128) break;
     case 256: CAC_COPY(256) break;

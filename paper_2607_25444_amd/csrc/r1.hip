@@ -71,13 +71,13 @@ hipError_t launch_r1_stream(const Grid &g, const Tiling &t, const DevParams &p, 
     const bool ntl = t.bx >= g.nx;
 #define CAC_R1S(NT_)                                                                                              \
     if (self)                                                                                                     \
-        k_r1_stream<NT_, true, false><<<t.ntiles, NT_, 0, s>>>(g, t, p, F.f[0], F.phi[pcur], F.nbr, F.twall, F.pstar0,     \
+        k_r1_stream<NT_, true, false><<<t.ntiles, NT_, t.hyd_lds, s>>>(g, t, p, F.f[0], F.phi[pcur], F.nbr, F.twall, F.pstar0,     \
                                                                F.u, F.f[1], F.flag);                              \
     else if (ntl)                                                                                                 \
-        k_r1_stream<NT_, false, true><<<t.ntiles, NT_, 0, s>>>(g, t, p, F.f[0], F.phi[pcur], F.nbr, F.twall, F.pstar0,     \
+        k_r1_stream<NT_, false, true><<<t.ntiles, NT_, t.hyd_lds, s>>>(g, t, p, F.f[0], F.phi[pcur], F.nbr, F.twall, F.pstar0,     \
                                                                F.u, F.f[1], F.flag);                              \
     else                                                                                                          \
-        k_r1_stream<NT_, false, false><<<t.ntiles, NT_, 0, s>>>(g, t, p, F.f[0], F.phi[pcur], F.nbr, F.twall, F.pstar0,    \
+        k_r1_stream<NT_, false, false><<<t.ntiles, NT_, t.hyd_lds, s>>>(g, t, p, F.f[0], F.phi[pcur], F.nbr, F.twall, F.pstar0,    \
                                                                 F.u, F.f[1], F.flag);
     switch (t.bx * t.by * t.bz) {
     case 128: CAC_R1S(128) break;

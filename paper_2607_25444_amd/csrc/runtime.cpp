@@ -89,6 +89,22 @@ DevParams make_dev_params(const cac_params &p)
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// LDS to reserve per collide-stream workgroup of nt threads so that at most
+// 4 waves per SIMD (16 per CU) are resident: the workgroups that fit a CU's
+// LDS then number 16 / (nt / 64).  The collide-stream uses no LDS; with fewer
+// workgroups in flight fewer 27-plane streams compete for HBM, and it runs
+// 5-6% faster than at its register-limited 6-7 waves per SIMD.  0 when the
+// device does not report its LDS size.
+uint32_t hydro_lds_reserve(int dev, int nt)
+{
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess || lds <= 0)
+        return 0u;
+    const int wgs = std::max(1, 16 / (nt / 64));
+    const uint32_t r = (uint32_t)(lds / (wgs + 1) + 64);
+    return r <= 65536u ? r : 0u;
+}
+
 Tiling make_tiling(const Grid &g, int bx, int by, int bz)
 {
     Tiling t{};
@@ -323,6 +339,7 @@ cac_status cac_init(cac_handle **hp, int nx, int ny, int nz, const cac_params *p
         delete h;
         return CAC_ERR_HIP;
     }
+    h->t.hyd_lds = hydro_lds_reserve(h->dev, bx * by * bz);
     Fields &F = h->F;
     const size_t Nf = (size_t)N;
     for (int k = 0; k < 2; ++k) {
@@ -576,6 +593,7 @@ cac_status cac_set_launch(cac_handle *h, int bx, int by, int bz, int phase_tile,
     if (phase_tile < 0 || phase_tile > 6) return fail(h, CAC_ERR_ARG, "unsupported phase tile %d", phase_tile);
     Tiling t = make_tiling(h->g, bx, by, bz);
     t.phase = phase_tile;
+    t.hyd_lds = hydro_lds_reserve(h->dev, nt);
     if (t.ntiles > h->partial_cap) return fail(h, CAC_ERR_ARG, "too many tiles");
     h->t = t;
     if (h->geometry) HIPCHK(h, launch_tile_walls(h->g, h->t, h->F, h->stream));
