@@ -296,14 +296,14 @@ hipError_t launch_br1_rebuild(const BatchPtrs &B, int code, const uint2 *items, 
 }
 
 hipError_t launch_br1_stream(const BatchPtrs &B, const float *pstar0, int nt, const uint2 *items, uint32_t nitems,
-                             int cur, bool self, hipStream_t s)
+                             uint32_t lds, int cur, bool self, hipStream_t s)
 {
     if (!nitems) return hipSuccess;
 #define CAC_BR1S(NT_)                                                                        \
     if (self)                                                                                \
-        k_br1_stream<NT_, true><<<nitems, NT_, 0, s>>>(B, B.dom, items, pstar0, cur);       \
+        k_br1_stream<NT_, true><<<nitems, NT_, lds, s>>>(B, B.dom, items, pstar0, cur);       \
     else                                                                                     \
-        k_br1_stream<NT_, false><<<nitems, NT_, 0, s>>>(B, B.dom, items, pstar0, cur);
+        k_br1_stream<NT_, false><<<nitems, NT_, lds, s>>>(B, B.dom, items, pstar0, cur);
     switch (nt) {
     case 128: CAC_BR1S(128) break;
     case 256: CAC_BR1S(256) break;
@@ -323,22 +323,22 @@ hipError_t launch_bghost(const BatchPtrs &B, uint32_t nwall, int cur, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_bhydro(const BatchPtrs &B, int nt, const uint2 *items, uint32_t nitems, uint32_t grid, int cur,
+hipError_t launch_bhydro(const BatchPtrs &B, int nt, const uint2 *items, uint32_t nitems, uint32_t grid, uint32_t lds, int cur,
                          hipStream_t s)
 {
     if (!nitems) return hipSuccess;
     switch (nt) {
     case 128:
-        if (grid >= nitems) k_bhydro1<128><<<nitems, 128, 0, s>>>(B, B.dom, items, nitems, cur);
-        else k_bhydro<128><<<grid, 128, 0, s>>>(B, B.dom, items, nitems, cur);
+        if (grid >= nitems) k_bhydro1<128><<<nitems, 128, lds, s>>>(B, B.dom, items, nitems, cur);
+        else k_bhydro<128><<<grid, 128, lds, s>>>(B, B.dom, items, nitems, cur);
         break;
     case 256:
-        if (grid >= nitems) k_bhydro1<256><<<nitems, 256, 0, s>>>(B, B.dom, items, nitems, cur);
-        else k_bhydro<256><<<grid, 256, 0, s>>>(B, B.dom, items, nitems, cur);
+        if (grid >= nitems) k_bhydro1<256><<<nitems, 256, lds, s>>>(B, B.dom, items, nitems, cur);
+        else k_bhydro<256><<<grid, 256, lds, s>>>(B, B.dom, items, nitems, cur);
         break;
     case 512:
-        if (grid >= nitems) k_bhydro1<512><<<nitems, 512, 0, s>>>(B, B.dom, items, nitems, cur);
-        else k_bhydro<512><<<grid, 512, 0, s>>>(B, B.dom, items, nitems, cur);
+        if (grid >= nitems) k_bhydro1<512><<<nitems, 512, lds, s>>>(B, B.dom, items, nitems, cur);
+        else k_bhydro<512><<<grid, 512, lds, s>>>(B, B.dom, items, nitems, cur);
         break;
     default: return hipErrorInvalidValue;
     }
@@ -400,15 +400,15 @@ hipError_t launch_bvolume(const BatchPtrs &B, int nt, const uint2 *items, uint32
     return hipGetLastError();
 }
 
-int batch_blocks_per_cu(int kind, int code)
+int batch_blocks_per_cu(int kind, int code, uint32_t lds)
 {
     int nb = 0;
     hipError_t e = hipSuccess;
     if (kind == 0) {
         switch (code) {
-        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bhydro<128>, 128, 0); break;
-        case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bhydro<256>, 256, 0); break;
-        case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bhydro<512>, 512, 0); break;
+        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bhydro<128>, 128, lds); break;
+        case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bhydro<256>, 256, lds); break;
+        case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bhydro<512>, 512, lds); break;
         default: return 0;
         }
     } else {

@@ -17,6 +17,6 @@ hipError_t launch_br1_rebuild(const BatchPtrs &B, int phase_code, const uint2 *i
 // step after the initial state, which pulls each node's own equilibrium
 // (p*0 from pstar0, u0 from B.u).  cur: parity of the phase-field buffers.
 hipError_t launch_br1_stream(const BatchPtrs &B, const float *pstar0, int nt, const uint2 *items, uint32_t nitems,
-                             int cur, bool self, hipStream_t s);
+                             uint32_t lds, int cur, bool self, hipStream_t s);
 
 }  // namespace cac

@@ -58,6 +58,7 @@ struct cac_batch {
     uint2 *d_hitems = nullptr, *d_pitems = nullptr;
     size_t hcap = 0, pcap = 0;
     uint32_t nh = 0, np = 0, hgrid = 0, pgrid = 0;
+    uint32_t hlds = 0;            // LDS each collide-stream workgroup reserves (occupancy cap)
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int cur = 0;
     long long steps = 0;
@@ -179,7 +180,8 @@ cac_status apply_schedule(cac_batch *b, const Schedule &s)
     }
     b->nh = (uint32_t)hi.size();
     b->np = (uint32_t)pi.size();
-    const int hb = std::max(1, batch_blocks_per_cu(0, nt));
+    b->hlds = hydro_lds_reserve(b->dev, nt);
+    const int hb = std::max(1, batch_blocks_per_cu(0, nt, b->hlds));
     const int pb = std::max(1, batch_blocks_per_cu(1, s.phase));
     if (s.mult == 0) {
         b->hgrid = b->nh;
@@ -213,9 +215,9 @@ cac_status run_bstep(cac_batch *b, hipStream_t s, bool self = false)
     if (b->coll) {
         // one workgroup per item whatever the grid multiplier
         if (!self) BCHK(b, launch_br1_rebuild(b->B, b->sch.phase, b->d_pitems, b->np, s));
-        BCHK(b, launch_br1_stream(b->B, b->pstar0, nt, b->d_hitems, b->nh, c, self, s));
+        BCHK(b, launch_br1_stream(b->B, b->pstar0, nt, b->d_hitems, b->nh, b->hlds, c, self, s));
     } else {
-        BCHK(b, launch_bhydro(b->B, nt, b->d_hitems, b->nh, b->hgrid, c, s));
+        BCHK(b, launch_bhydro(b->B, nt, b->d_hitems, b->nh, b->hgrid, b->hlds, c, s));
     }
     BCHK(b, launch_bphase(b->B, b->sch.phase, b->d_pitems, b->np, b->pgrid, c, s));
     BCHK(b, launch_bvolume(b->B, nt, b->d_hitems, b->nh, b->hgrid, c ^ 1, s));
@@ -635,9 +637,9 @@ cac_status cac_batch_profile(cac_batch *b, int nsteps, double *ms)
         if (b->coll) {
             const bool self = b->steps == 0;
             if (!self) BCHK(b, launch_br1_rebuild(b->B, b->sch.phase, b->d_pitems, b->np, b->stream));
-            BCHK(b, launch_br1_stream(b->B, b->pstar0, nt, b->d_hitems, b->nh, c, self, b->stream));
+            BCHK(b, launch_br1_stream(b->B, b->pstar0, nt, b->d_hitems, b->nh, b->hlds, c, self, b->stream));
         } else {
-            BCHK(b, launch_bhydro(b->B, nt, b->d_hitems, b->nh, b->hgrid, c, b->stream));
+            BCHK(b, launch_bhydro(b->B, nt, b->d_hitems, b->nh, b->hgrid, b->hlds, c, b->stream));
         }
         BCHK(b, hipEventRecord(e[2], b->stream));
         BCHK(b, launch_bphase(b->B, b->sch.phase, b->d_pitems, b->np, b->pgrid, c, b->stream));

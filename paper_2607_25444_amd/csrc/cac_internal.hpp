@@ -139,14 +139,16 @@ struct BatchPtrs {
 // order of the block schedule.  grid = number of persistent workgroups.
 hipError_t launch_bghost(const BatchPtrs &B, uint32_t nwall, int cur, hipStream_t s);
 hipError_t launch_bitem_walls(const BatchPtrs &B, int nt, uint2 *items, uint32_t nitems, hipStream_t s);
-hipError_t launch_bhydro(const BatchPtrs &B, int nt, const uint2 *items, uint32_t nitems, uint32_t grid, int cur,
+hipError_t launch_bhydro(const BatchPtrs &B, int nt, const uint2 *items, uint32_t nitems, uint32_t grid, uint32_t lds, int cur,
                          hipStream_t s);
 hipError_t launch_bphase(const BatchPtrs &B, int phase_code, const uint2 *items, uint32_t nitems, uint32_t grid,
                          int cur, hipStream_t s);
 hipError_t launch_bvolume(const BatchPtrs &B, int nt, const uint2 *items, uint32_t nitems, uint32_t grid, int cur_next,
                           hipStream_t s);
 // resident workgroups per CU of a batched kernel (kind 0 hydro / 1 phase), 0 on failure
-int batch_blocks_per_cu(int kind, int code);
+int batch_blocks_per_cu(int kind, int code, uint32_t lds = 0);
+// LDS bytes a collide-stream workgroup of nt threads reserves (see Tiling::hyd_lds)
+uint32_t hydro_lds_reserve(int dev, int nt);
 void phase_shape_of(int code, int &bx, int &by);  // code 1..6
 PhaseTiling phase_tiling(const Grid &g, int bx, int by);
 
