@@ -21,6 +21,8 @@ line:
   spreading  the same for the 256 x 256 x 128 spreading workload
   r1, batched, adjoint   the gradient-form collision, the 64-domain batch and
              the reverse-mode sweep, each beside the plain step
+  adjoint_resident   the same reverse-mode sweep with the whole rollout kept in
+             HBM (one segment, no replay), when the device has the room
   cpu_baseline  the FP64 oracle timed on the host on a bounded sample
 """
 from __future__ import annotations
@@ -545,6 +547,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=1000)
     ap.add_argument("--adjoint-K", type=int, default=50)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-adjoint-resident", action="store_true",
+                    help="skip the adjoint run that keeps the whole rollout in HBM (K = adjoint steps)")
     ap.add_argument("--r1-steps", type=int, default=200)
     ap.add_argument("--no-r1", action="store_true", help="skip the gradient-form collision (collision = 1)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -671,6 +675,20 @@ def main():
         log("[bench] adjoint workload ...")
         rec["adjoint"] = bench_adjoint(torch, capi, tuning, W, args.adjoint_steps, args.adjoint_K, args.seed)
         log(f"[bench] adjoint {rec['adjoint']}")
+    if not args.no_adjoint and not args.no_adjoint_resident:
+        # the same rollout as one segment: the recorded sweep keeps every step
+        # in the rings (about 128 B per node and step), and nothing is replayed
+        torch.cuda.empty_cache()
+        need = 128 * W.adjoint_128(args.seed).N * args.adjoint_steps * 1.05 + (4 << 30)
+        free_b, _ = torch.cuda.mem_get_info()
+        if free_b > need:
+            log("[bench] adjoint workload, whole rollout resident in HBM ...")
+            rec["adjoint_resident"] = bench_adjoint(torch, capi, tuning, W, args.adjoint_steps, args.adjoint_steps,
+                                                    args.seed)
+            log(f"[bench] adjoint_resident {rec['adjoint_resident']}")
+        else:
+            rec["adjoint_resident"] = {"skipped": f"needs {need / 2**30:.0f} GiB, {free_b / 2**30:.0f} GiB free"}
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host ...")
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, W, capi, launch)

@@ -255,10 +255,15 @@ cac_status cac_destroy(cac_handle *h);
 /* Advance nsteps steps from the current state, exactly as cac_step, and record
  * the sweep for cac_tape_backward: the state (populations, phi, previous
  * ghosts) is copied every K steps (checkpoints, ceil(nsteps/K) x 29 N floats)
- * together with the contact angles in use.  cac_set_state and
+ * together with the contact angles in use.  The last segment (the steps after
+ * the last checkpoint) runs through the reverse sweep's rings, which are
+ * allocated here (about 32 N floats per step of a segment), so that segment is
+ * never replayed; the live state afterwards is the one cac_step would leave,
+ * bit for bit.  With K >= nsteps the whole rollout is kept (about 128 bytes
+ * per node and step) and nothing is replayed.  cac_set_state and
  * cac_set_geometry discard the recording.  Asynchronous.
- * Errors: CAC_ERR_ARG (nsteps or K < 1), CAC_ERR_STATE (no state),
- * CAC_ERR_ALLOC. */
+ * Errors: CAC_ERR_ARG (nsteps or K < 1), CAC_ERR_STATE (no state, inside a
+ * debug step, collision = 1 or ghost_localization = 0), CAC_ERR_ALLOC. */
 cac_status cac_tape_forward(cac_handle *h, int nsteps, int K);
 
 /* Reverse sweep of the recorded sweep.  d_phibar (device, N floats): cotangent
@@ -268,8 +273,11 @@ cac_status cac_tape_forward(cac_handle *h, int nsteps, int K);
  * (zero for skipped wall nodes); d_phibar0 (device, N floats, or NULL) =
  * dL/dphi of the phase field passed to cac_set_state (fluid values and initial
  * ghosts).  Each segment of K steps is replayed from its checkpoint into rings
- * of about (33 K + 70) N floats (allocated on first use), then reversed step
- * by step.  The live state is not changed.  Asynchronous.
+ * of about (33 K + 70) N floats, then reversed step by step; the last segment
+ * is already in the rings after cac_tape_forward (and stays there for a
+ * repeated call when it is the only segment).  With room for a second set of
+ * rings, the replay of the next segment runs on a second stream while the
+ * current one is reversed.  The live state is not changed.  Asynchronous.
  * Errors: CAC_ERR_ARG (null pointer), CAC_ERR_STATE (nothing recorded, or the
  * geometry changed since), CAC_ERR_ALLOC. */
 cac_status cac_tape_backward(cac_handle *h, const float *d_phibar, double *d_dtheta, float *d_phibar0);

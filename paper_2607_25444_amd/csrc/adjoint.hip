@@ -137,6 +137,16 @@ __global__ __launch_bounds__(256) void k_add_fluid(uint32_t N, const uint8_t *__
     if (n < N && !solid[n]) pb[n] += (float)rs[3];
 }
 
+// dst = src on the fluid nodes of `planes` planes of N floats; the solid
+// entries of dst keep their values (no step writes them).
+__global__ __launch_bounds__(256) void k_copy_fluid(uint32_t N, uint32_t planes, const uint8_t *__restrict__ solid,
+                                                    const float *__restrict__ src, float *__restrict__ dst)
+{
+    const uint32_t n = blockIdx.x * 256u + threadIdx.x;
+    if (n >= N || solid[n]) return;
+    for (uint32_t q = 0; q < planes; ++q) dst[(size_t)q * N + n] = src[(size_t)q * N + n];
+}
+
 template <int NT>
 __global__ __launch_bounds__(NT) void k_adj_main(Grid g, Tiling t, DevParams p, AdjStep S)
 {
@@ -328,6 +338,13 @@ hipError_t launch_adj_fix(const Grid &g, const AdjStep &S, hipStream_t s)
 {
     if (S.nnear == 0) return hipSuccess;
     k_adj_fix<<<nblocks(S.nnear, 256), 256, 0, s>>>(g, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_fluid(const Grid &g, const uint8_t *solid, int planes, const float *src, float *dst,
+                             hipStream_t s)
+{
+    k_copy_fluid<<<nblocks(g.N, 256), 256, 0, s>>>(g.N, (uint32_t)planes, solid, src, dst);
     return hipGetLastError();
 }
 

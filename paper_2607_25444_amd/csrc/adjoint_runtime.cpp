@@ -5,6 +5,9 @@
 // its ghosts, velocity, phi before the volume correction), then runs the
 // reverse steps of the segment backwards.  Device memory is bounded by
 // ceil(nsteps/K) checkpoints of 29 N words plus rings of about 33 K N words.
+// The recorded sweep runs its last segment straight into the rings, so that
+// segment is never replayed; with K >= nsteps (one segment, about 128 bytes
+// per node and step: 134 GB for 1000 steps of 128x128x64) nothing is.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,6 +29,7 @@ struct AdjTape {
     // One or two sets of segment rings: with two, the replay of the next
     // segment (on the auxiliary stream) runs while this one is reversed.
     int nsets = 0;
+    bool last_in_rings = false;    // ring set 0 holds the last segment, left by the recorded sweep
     std::vector<float *> rf[2];    // K+1 population sets: rf[j] enters step j of the segment
     std::vector<float *> rphi[2];  // K+2 phase fields: rphi[j+1] = phi with the ghosts of step j
     std::vector<float *> ru[2];    // K velocities (zero on solid nodes)
@@ -263,11 +267,13 @@ cac_status cac_tape_forward(cac_handle *h, int nsteps, int K)
     if (!h) return CAC_ERR_ARG;
     if (nsteps < 1 || K < 1) return fail(h, CAC_ERR_ARG, "nsteps and K must be >= 1");
     if (!h->state) return fail(h, CAC_ERR_STATE, "cac_set_state must come first");
+    if (h->sub != 0) return fail(h, CAC_ERR_STATE, "a step was started with cac_debug_substep");
     if (h->prm.collision != 0) return fail(h, CAC_ERR_STATE, "the adjoint is built for collision = 0");
     if (h->prm.ghost_localization != 1)
         return fail(h, CAC_ERR_STATE, "the adjoint is built for the localisation factor of Eq. (47)");
     AdjTape &T = *tape_of(h);
     T.recorded = false;
+    T.last_in_rings = false;
     const size_t N = h->g.N;
     const int nck = (nsteps + K - 1) / K;
     while ((int)T.ck.size() < nck) {
@@ -282,6 +288,12 @@ cac_status cac_tape_forward(cac_handle *h, int nsteps, int K)
     }
     if (nwall)
         HIPCHK(h, hipMemcpyAsync(T.theta, h->F.theta, nwall * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    // The last segment runs as the replay would, into ring set 0 (which the
+    // reverse sweep needs in any case), and its end state is copied back to
+    // the handle; the steps before it are ordinary steps.
+    const int last0 = (nck - 1) * K;
+    T.K = K;
+    if (!alloc_ring_set(h, T, 0)) return fail(h, CAC_ERR_ALLOC, "adjoint ring");
     for (int n = 0; n < nsteps; ++n) {
         if (n % K == 0) {
             float *c = T.ck[n / K];
@@ -291,11 +303,42 @@ cac_status cac_tape_forward(cac_handle *h, int nsteps, int K)
             HIPCHK(h, hipMemcpyAsync(c + 28 * N, h->F.phi[cur ^ 1], N * sizeof(float), hipMemcpyDeviceToDevice,
                                      h->stream));
         }
-        cac_status st = cac_step(h, 1);
-        if (st != CAC_OK) return st;
+        if (n == last0) {
+            const int cur = h->cur;
+            HIPCHK(h, hipMemcpyAsync(T.rf[0][0], h->F.f[cur], 27 * N * sizeof(float), hipMemcpyDeviceToDevice,
+                                     h->stream));
+            HIPCHK(h, hipMemcpyAsync(T.rphi[0][1], h->F.phi[cur], N * sizeof(float), hipMemcpyDeviceToDevice,
+                                     h->stream));
+            HIPCHK(h, hipMemcpyAsync(T.rphi[0][0], h->F.phi[cur ^ 1], N * sizeof(float), hipMemcpyDeviceToDevice,
+                                     h->stream));
+        }
+        if (n >= last0) {
+            cac_status st = replay_step(h, T, 0, n - last0, h->stream);
+            if (st != CAC_OK) return st;
+        } else {
+            cac_status st = cac_step(h, 1);
+            if (st != CAC_OK) return st;
+        }
     }
+    {
+        // The handle continues from the end of the last segment, in the state
+        // the in-place steps leave.  No step writes populations or velocity
+        // on solid nodes, so only the fluid entries are copied.  The current
+        // phi holds the corrected fluid values and, on solid nodes, what that
+        // buffer held before (the ghosts of the step before last): what the
+        // correction writes when given the ring entry of that step as phi-hat.
+        const int L = nsteps - last0, cur = h->cur ^ (L & 1);  // the parity L in-place steps end on
+        HIPCHK(h, launch_copy_fluid(h->g, h->F.solid, 27, T.rf[0][L], h->F.f[cur], h->stream));
+        HIPCHK(h, launch_volume_copy(h->g, h->t, h->dp, h->F, T.rps[0][L - 1], T.rphi[0][L - 1], h->F.phi[cur],
+                                     h->stream));
+        HIPCHK(h, hipMemcpyAsync(h->F.phi[cur ^ 1], T.rphi[0][L], N * sizeof(float), hipMemcpyDeviceToDevice,
+                                 h->stream));
+        HIPCHK(h, launch_copy_fluid(h->g, h->F.solid, 3, T.ru[0][L - 1], h->F.u, h->stream));
+        h->cur = cur;
+        h->steps += L;
+    }
+    T.last_in_rings = true;
     T.nsteps = nsteps;
-    T.K = K;
     T.rec_serial = h->geom_serial;
     T.recorded = true;
     return CAC_OK;
@@ -326,11 +369,17 @@ cac_status cac_tape_backward(cac_handle *h, const float *d_phibar, double *d_dth
     // after the reverse that last used its set, and each reverse after its
     // replay.  With one set the two alternate on the handle stream.
     const bool overlap = T.nsets == 2;
+    // the last segment is in ring set 0 when the recorded sweep left it there
+    // and no earlier reverse sweep has reused the set since
+    const bool have_last = T.last_in_rings;
+    T.last_in_rings = have_last && nck == 1;
     if (overlap) {
         HIPCHK(h, hipEventRecord(T.joined, h->stream));  // the aux stream starts after everything queued so far
         HIPCHK(h, hipStreamWaitEvent(T.aux, T.joined, 0));
-        st = replay_segment(h, T, nck - 1, 0, T.aux);
-        if (st != CAC_OK) return st;
+        if (!have_last) {
+            st = replay_segment(h, T, nck - 1, 0, T.aux);
+            if (st != CAC_OK) return st;
+        }
         HIPCHK(h, hipEventRecord(T.ready[0], T.aux));
     }
     for (int seg = nck - 1; seg >= 0; --seg) {
@@ -344,7 +393,7 @@ cac_status cac_tape_backward(cac_handle *h, const float *d_phibar, double *d_dth
                 HIPCHK(h, hipEventRecord(T.ready[k ^ 1], T.aux));
             }
             HIPCHK(h, hipStreamWaitEvent(h->stream, T.ready[k], 0));
-        } else {
+        } else if (!(have_last && seg == nck - 1)) {
             st = replay_segment(h, T, seg, 0, h->stream);
             if (st != CAC_OK) return st;
         }

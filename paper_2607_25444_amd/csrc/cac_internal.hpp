@@ -237,6 +237,9 @@ hipError_t launch_adj_main(const Grid &g, const Tiling &t, const DevParams &p, c
 hipError_t launch_adj_assemble(const Grid &g, const Tiling &t, const AdjStep &S, hipStream_t s);
 hipError_t launch_adj_wall(const Grid &g, const DevParams &p, const AdjStep &S, hipStream_t s);
 hipError_t launch_adj_fix(const Grid &g, const AdjStep &S, hipStream_t s);
+// dst = src on the fluid nodes of `planes` planes of N floats (solid entries untouched)
+hipError_t launch_copy_fluid(const Grid &g, const uint8_t *solid, int planes, const float *src, float *dst,
+                             hipStream_t s);
 // pb += rs[3] on fluid nodes (the path of dL/dphi0 through the target volume)
 hipError_t launch_adj_mtarget(const Grid &g, const uint8_t *solid, float *pb, const double *rs, hipStream_t s);
 // seed = phi - target on fluid nodes (0 elsewhere) and out[0] = 1/2 sum_fluid (phi - target)^2 in FP64

@@ -696,11 +696,11 @@ cac_status cac_save_state(cac_handle *h, void *d_buf, size_t bytes)
     const size_t N = h->g.N;
     const int c = h->cur;
     char *b = (char *)d_buf;
-    uint64_t hdr[3] = {kStateMagic, (uint64_t)N, (uint64_t)h->steps};
-    const uint64_t coll = (uint64_t)h->prm.collision;
+    // header: magic, N, step count, target volume (filled from the device below),
+    // collision setting, zeros to 64 bytes
+    uint64_t hdr[kStateHeader / 8] = {kStateMagic, (uint64_t)N, (uint64_t)h->steps, 0u, (uint64_t)h->prm.collision};
     HIPCHK(h, hipStreamSynchronize(h->stream));
     HIPCHK(h, hipMemcpy(b, hdr, sizeof hdr, hipMemcpyHostToDevice));
-    HIPCHK(h, hipMemcpy(b + 32, &coll, sizeof coll, hipMemcpyHostToDevice));
     HIPCHK(h, hipMemcpyAsync(b + 24, h->F.scal, sizeof(double), hipMemcpyDeviceToDevice, h->stream));
     float *a = (float *)(b + kStateHeader);
     // the 27 population planes, or the record planes of the gradient-form path

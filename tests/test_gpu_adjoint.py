@@ -102,7 +102,7 @@ def test_checkpoint_interval_does_not_change_the_gradient():
     shape = (20, 18, 16)
     solid, phi0, theta, target, params = CASES["droplet"](shape)
     ref = None
-    for K in (1, 3, 7, 9):
+    for K in (1, 3, 7, 9, 20):
         L, dth, dphi0, _, _ = gpu_grad(shape, solid, phi0, theta, target, params, 9, K)
         if ref is None:
             ref = (L, dth, dphi0)
@@ -110,6 +110,71 @@ def test_checkpoint_interval_does_not_change_the_gradient():
             assert L == ref[0]
             assert np.array_equal(dth, ref[1])
             assert np.array_equal(dphi0, ref[2])
+
+
+@pytest.mark.parametrize("K", [4, 9, 20])
+def test_recorded_sweep_leaves_the_state_of_plain_steps(K):
+    """The recorded sweep runs its last segment through the rings (K = 4: one step,
+    K >= 9: all nine) and hands the end state back to the handle.  The saved state
+    (populations, phi in both buffers with their ghosts, velocity, step count)
+    must equal that of nine plain steps bit for bit, and so must the state three
+    plain steps later."""
+    from paper_2607_25444_amd import capi
+    shape = (20, 18, 16)
+    solid, phi0, theta, target, params = CASES["droplet"](shape)
+
+    def run(record):
+        s = capi.Sim(shape, params)
+        s.set_geometry(solid, theta)
+        s.set_state(phi0)
+        if record:
+            s.tape_forward(9, K)
+        else:
+            s.step(9)
+        a = s.save_state().cpu().numpy()
+        s.step(3)
+        b = s.save_state().cpu().numpy()
+        s.sync()
+        s.close()
+        return a, b
+
+    def where(x, y):
+        """Sections of the saved state (64-byte header, then float planes) that differ."""
+        n = int(np.prod(shape))
+        bounds = [("header", 0, 64), ("populations", 64, 64 + 108 * n), ("phi", 64 + 108 * n, 64 + 112 * n),
+                  ("phi previous", 64 + 112 * n, 64 + 116 * n), ("u", 64 + 116 * n, 64 + 128 * n),
+                  ("p*0", 64 + 128 * n, 64 + 132 * n)]
+        return [name for name, lo, hi in bounds if not np.array_equal(x[lo:hi], y[lo:hi])]
+
+    a0, b0 = run(False)
+    a1, b1 = run(True)
+    assert a0.size == a1.size == 64 + 132 * int(np.prod(shape))
+    assert np.array_equal(a0, a1), where(a0, a1)
+    assert np.array_equal(b0, b1), where(b0, b1)
+
+
+@pytest.mark.parametrize("K", [3, 9])
+def test_reverse_sweep_can_be_repeated(K):
+    """A second reverse sweep of the same recording gives the same bits: with one
+    segment (K = 9) the rings still hold it; with several (K = 3) the last
+    segment, overwritten by the first sweep, is replayed from its checkpoint."""
+    from paper_2607_25444_amd import capi
+    shape = (20, 18, 16)
+    solid, phi0, theta, target, params = CASES["droplet"](shape)
+    s = capi.Sim(shape, params)
+    s.set_geometry(solid, theta)
+    s.set_state(phi0)
+    s.tape_forward(9, K)
+    _, seed = s.loss(target)
+    out = []
+    for _ in range(2):
+        dth, dphi0 = s.tape_backward(seed)
+        s.sync()
+        out.append((dth.cpu().numpy(), dphi0.cpu().numpy()))
+    s.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    assert np.abs(out[0][0]).max() > 0.0
 
 
 def test_gradient_matches_oracle_finite_differences(orc):
