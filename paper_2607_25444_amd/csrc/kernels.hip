@@ -13,8 +13,9 @@
 //                there by P (which forms the fluid values from its own phi planes)
 //   nbr[n]       bit 0: node is solid; bit i: node + c_i is solid
 //
-// Every kernel bounds-checks its node against the grid; bulk kernels map
-// workgroups to tiles so that each XCD works on a contiguous range of tiles.
+// Every kernel bounds-checks its node against the grid.  The phase kernel maps
+// workgroups to tiles so that each XCD works on a contiguous range of tiles;
+// the collide-stream keeps the hardware's round-robin order.
 #include <algorithm>
 
 #include "step_device.hpp"
@@ -40,12 +41,13 @@ __global__ __launch_bounds__(NT) void k_hydro(Grid g, Tiling t, DevParams p, con
                                               const uint32_t *__restrict__ nbr, const uint8_t *__restrict__ twall,
                                               float *__restrict__ u, uint32_t *__restrict__ flag)
 {
-    // Workgroup order: with non-temporal loads nothing is re-read from L2, and
-    // the hardware's round-robin over the XCDs streams HBM best (3% faster on
-    // 256x256x128); with ordinary loads each XCD takes a contiguous range of
-    // tiles so that halo rows stay in its L2.
-    const uint32_t b = p.rev_order ? gridDim.x - 1u - blockIdx.x : blockIdx.x;
-    const uint32_t tile = NTL ? b : xcd_tile(b, t.ntiles);
+    // Workgroup order: the hardware's, workgroup b on XCD b mod 8.  At 4 waves
+    // per SIMD it streams HBM better than giving each XCD a contiguous range of
+    // tiles, with row-wide tiles and non-temporal loads (3% on 256x256x128)
+    // and with narrower tiles and ordinary loads alike (6% on 64x8 tiles of
+    // the 192-wide orifice lattice, whose halo rows are then re-read from the
+    // shared last-level cache instead of an XCD's L2).
+    const uint32_t tile = p.rev_order ? gridDim.x - 1u - blockIdx.x : blockIdx.x;
     // tiles away from every solid node skip the neighbour-mask load (4 B per node)
     hydro_node<NTL>(g, p, tile_node(g, t, tile), fin, fout, phi, nbr, u, flag, twall[tile] != 0);
 }

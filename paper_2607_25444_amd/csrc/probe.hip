@@ -12,7 +12,7 @@ template <int NT, bool NTL>
 __global__ __launch_bounds__(NT) void k_pull_copy(Grid g, Tiling t, const float *__restrict__ fin,
                                                   float *__restrict__ fout)
 {
-    const Node nd = tile_node(g, t, NTL ? blockIdx.x : xcd_tile(blockIdx.x, t.ntiles));
+    const Node nd = tile_node(g, t, blockIdx.x);
     if (!nd.in) return;
     const Offs o = node_offsets(g, nd.x, nd.y, nd.z);
     const uint32_t n = at<0, 0, 0>(o), N = g.N;

@@ -41,8 +41,8 @@ __global__ __launch_bounds__(CX *CY) void k_r1_rebuild(Grid g, PhaseTiling pt, D
     r1_rebuild_tile<CX, CY>(g, pt, xcd_tile(b, pt.ntiles), rec, u, nbr, fout);
 }
 
-// Workgroup order as in the local-moment kernel: the hardware's with
-// non-temporal loads, XCD-contiguous tiles otherwise.
+// Workgroup order as in the local-moment kernel: the hardware's (on 64x8
+// tiles of the 192-wide orifice lattice 3% faster than XCD-contiguous tiles).
 template <int NT, bool SELF, bool NTL>
 __global__ __launch_bounds__(NT) void k_r1_stream(Grid g, Tiling t, DevParams p, const float *__restrict__ fin,
                                                   const float *__restrict__ phi, const uint32_t *__restrict__ nbr,
@@ -50,8 +50,7 @@ __global__ __launch_bounds__(NT) void k_r1_stream(Grid g, Tiling t, DevParams p,
                                                   float *__restrict__ u, float *__restrict__ rec,
                                                   uint32_t *__restrict__ flag)
 {
-    const uint32_t b = p.rev_order ? gridDim.x - 1u - blockIdx.x : blockIdx.x;
-    const uint32_t tile = NTL ? b : xcd_tile(b, t.ntiles);
+    const uint32_t tile = p.rev_order ? gridDim.x - 1u - blockIdx.x : blockIdx.x;
     r1_stream_node<SELF, NTL>(g, p, tile_node(g, t, tile), fin, phi, nbr, pstar0, u, rec, flag, twall[tile] != 0);
 }
 
