@@ -337,7 +337,10 @@ class Sim:
 
     # -------------------------------------------------------------- adjoint
     def tape_forward(self, nsteps, K):
-        """Advance nsteps steps and record them (checkpoints every K) for tape_backward."""
+        """Advance nsteps steps and record them (checkpoints every K) for tape_backward.
+        The last segment is recorded into the reverse sweep's rings; K >= nsteps keeps
+        the whole rollout in device memory (about 128 B per node and step), and then
+        tape_backward replays nothing."""
         self._check(self.lib.cac_tape_forward(self.h, int(nsteps), int(K)))
         return self
 
