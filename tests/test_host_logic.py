@@ -6,8 +6,13 @@
   otherwise, and graph replay only for lattices of at most 2^22 nodes;
 * the workload generators are deterministic in their seed, and the benchmark's
   256 x 256 x 128 spreading lattice has the fluid and solid counts its JSON
-  line reports.
+  line reports;
+* ``bench.py`` refuses a run on more than one GPU before it touches a device.
 """
+import os
+import subprocess
+import sys
+
 import numpy as np
 
 from paper_2607_25444_amd import tuning, workloads as W
@@ -48,3 +53,14 @@ def test_spreading_256_counts():
     assert int((w.solid != 0).sum()) == 131072
     fl = w.solid == 0
     assert np.all((w.phi0[fl] >= 0.0) & (w.phi0[fl] <= 1.0))
+
+
+def test_bench_refuses_more_than_one_gpu():
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    bench = os.path.join(root, "bench.py")
+    for argv, env in ((["--gpus", "2"], {}), (["--gpus", "1"], {"WORLD_SIZE": "2"})):
+        r = subprocess.run([sys.executable, bench, *argv], capture_output=True, text=True, timeout=120,
+                           env=dict(os.environ, **env))
+        assert r.returncode == 2, r.stderr
+        assert "one GPU" in r.stderr
+        assert r.stdout == ""
